@@ -1,0 +1,164 @@
+/*
+ * dugks.h -- C ABI of the MI355X (gfx950) DUGKS library: one D2Q9 discrete
+ * unified gas-kinetic scheme time step for the conservative Allen-Cahn
+ * equation (Yang, Zhong & Zhuo, arXiv 2007.07760, Sec. II).
+ *
+ * The problem statement follows the paper: a periodic grid of unit cells
+ * (Sec. III), a prescribed velocity field (Sec. III, Eqs. 43-45), the mobility
+ * M_phi and interface width W of Eqs. (1)-(4), the CFL number C of Eq. (39)
+ * (dt = C since dx = sqrt(3RT) = 1) and the face reconstruction (central,
+ * Eq. 25, or upwind, Eq. 26).
+ *
+ * Conventions
+ *  - Every call returns a dugks_status; nothing is thrown and nothing aborts.
+ *    dugks_strerror() gives a static text for each code.
+ *  - The library owns only the plan (host memory).  Device memory is owned by
+ *    the caller: it allocates dugks_state_bytes() bytes (256-byte aligned) and
+ *    passes the pointer.  The library never allocates or frees device memory.
+ *  - Streams are the caller's (hipStream_t passed as void*; NULL = default
+ *    stream).  Calls that launch work are asynchronous on that stream; device
+ *    faults surface at the caller's next synchronisation.
+ *  - The step counter is the caller's: step n of the state is passed to each
+ *    call that depends on it (which of the two ping-pong buffers is current,
+ *    the time t_n = n dt of the velocity field, and the zero d(phi u)/dt of the
+ *    first step).
+ *  - Layout in the state: f~ as 9 velocity-major planes [i][y][x], x
+ *    contiguous with a row pitch, twice (ping-pong); the phi history plane twice;
+ *    a small header, coefficient and velocity tables and mass scratch.
+ *  - Plans are immutable after creation and may be shared between threads;
+ *    calls on distinct states may run concurrently on distinct streams.
+ *    Calls on one state must be ordered by the caller.
+ */
+#ifndef DUGKS_H
+#define DUGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DUGKS_OK = 0,
+  DUGKS_EINVAL = 1,       /* invalid argument (sizes, ranges, NULL, alignment) */
+  DUGKS_ENOMEM = 2,       /* host allocation failed                            */
+  DUGKS_EDEVICE = 3,      /* a HIP launch or runtime call failed               */
+  DUGKS_ENUMERIC = 4,     /* non-finite total mass                             */
+  DUGKS_EUNSUPPORTED = 5  /* valid request this build does not provide         */
+} dugks_status;
+
+typedef enum { DUGKS_F64 = 0, DUGKS_F32 = 1 } dugks_precision;
+
+/* Face reconstruction of fbar(x_b, t+h) = fbar+(x_b - xi h, t), Eq. (24):
+ *  CENTRAL2  Eq. (25): value and gradient at the face from the neighbouring
+ *            cells (mean of the two cells; normal difference; tangential
+ *            mean of central differences).                       (T2S2CD)
+ *  UPWIND3   Eq. (26): second-order Taylor expansion, with the factor 1/2,
+ *            about the upstream cell centre, isotropic D2Q9-weighted gradient
+ *            and Hessian; mean of the two sides when xi_i is parallel to the
+ *            face.                                                (T2S3)
+ *  CENTRAL4  Eq. (25) with fourth-order central estimates of the face value
+ *            and of both gradient components. */
+typedef enum { DUGKS_CENTRAL2 = 0, DUGKS_UPWIND3 = 1, DUGKS_CENTRAL4 = 2 } dugks_recon;
+
+/* Prescribed velocity u(x, y, t); cell centres at (i + 1/2, j + 1/2):
+ *  UNIFORM        u = p0, v = p1
+ *  ROTATION       u = -p0 (y - p2), v = p0 (x - p1)           (Eq. 43 form)
+ *  SINGLE_VORTEX  u = -p0 sin^2(pi X) sin(2 pi Y) cos(pi t / p1)
+ *                 v =  p0 sin(2 pi X) sin^2(pi Y) cos(pi t / p1),
+ *                 X = x / nx, Y = y / ny
+ *  DEFORMATION    u = -p0 sin(4 pi x/nx) sin(4 pi y/ny) cos(pi t / p1)
+ *                 v = -p0 cos(4 pi x/nx) cos(4 pi y/ny) cos(pi t / p1)  (Eq. 45)
+ *  ARRAYS         not provided by this build (DUGKS_EUNSUPPORTED). */
+typedef enum {
+  DUGKS_VEL_UNIFORM = 0,
+  DUGKS_VEL_ROTATION = 1,
+  DUGKS_VEL_SINGLE_VORTEX = 2,
+  DUGKS_VEL_DEFORMATION = 3,
+  DUGKS_VEL_ARRAYS = 4
+} dugks_vel_kind;
+
+/* flags */
+#define DUGKS_FLAG_DTPHIU_ZERO 1u /* drop d(phi u)/dt from the source (test hook) */
+
+typedef struct {
+  int32_t nx, ny;          /* cells per side, periodic; each in [8, 65536]         */
+  double mobility;         /* M_phi > 0, finite; tau = M_phi / RT = 3 M_phi       */
+  double width;            /* W > 0 cells; +INFINITY switches the theta term off  */
+  double cfl;              /* C in (0, 1]; dt = C, h = dt / 2                     */
+  int32_t recon;           /* dugks_recon                                        */
+  int32_t precision;       /* dugks_precision of the stored f~ and phi            */
+  int32_t vel_kind;        /* dugks_vel_kind                                     */
+  int32_t flags;           /* DUGKS_FLAG_*                                       */
+  double vel_param[6];     /* p0.. of the velocity kind; finite                  */
+  int32_t tile_rows;       /* rows one wavefront marches; 0 = library default    */
+  int32_t reserved;        /* must be 0                                          */
+} dugks_params;
+
+typedef struct dugks_plan dugks_plan;
+
+/* Validate p and build an immutable plan (stencil coefficients of the chosen
+ * reconstruction, collision coefficients, launch geometry).  Host-only: no HIP
+ * call is made.  Errors: EINVAL (p or out NULL, a field out of range),
+ * EUNSUPPORTED (ARRAYS velocity), ENOMEM. */
+int dugks_plan_create(const dugks_params *p, dugks_plan **out);
+void dugks_plan_destroy(dugks_plan *plan);
+
+/* Bytes of device memory one state needs (caller allocates, 256-B aligned). */
+size_t dugks_state_bytes(const dugks_plan *plan);
+
+/* Write the first state (step 0) from phi0 (device, FP64, [ny][nx] dense):
+ * f~^0 = feq(phi0, u(x, 0)) - (dt/2) S^0 with d(phi u)/dt = 0, and the
+ * coefficient and velocity tables of the plan.  Blocks the calling thread
+ * until the work queued on `stream` is done (the tables are staged from host
+ * memory).  Errors: EINVAL (NULL, misaligned state), EDEVICE. */
+int dugks_init(const dugks_plan *plan, void *state, const double *phi0_dev,
+               void *stream);
+
+/* Advance the state from step `step` by `nsteps` T2 steps (Eqs. 21-28 with the
+ * Eq. 15 update form): one fused face-reconstruction + flux + update kernel per
+ * step.  Asynchronous on `stream`.  Errors: EINVAL (NULL, step < 0,
+ * nsteps < 0), EDEVICE. */
+int dugks_step(const dugks_plan *plan, void *state, int64_t step,
+               int64_t nsteps, void *stream);
+
+/* phi = sum_i f~_i (Eq. 30) of the state at `step`, written to phi_out_dev as
+ * [ny][nx] dense elements of the plan's precision.  Asynchronous. */
+int dugks_phi(const dugks_plan *plan, const void *state, int64_t step,
+              void *phi_out_dev, void *stream);
+
+/* The 9 distributions f~_i of the state at `step`, written to out_dev as
+ * [9][ny][nx] dense elements of the plan's precision (velocity-major, paper
+ * order of Sec. II.B.2).  Asynchronous.  Errors: EINVAL, EDEVICE. */
+int dugks_distributions(const dugks_plan *plan, const void *state, int64_t step,
+                        void *out_dev, void *stream);
+
+/* Total mass sum(phi) of the state at `step`, FP64, Neumaier-compensated, with
+ * a fixed reduction order (deterministic), written to *mass_out_dev (device).
+ * Uses the state's scratch.  Asynchronous; the caller checks the value it
+ * reads back (a non-finite total means the state has blown up).
+ * Errors: EINVAL, EDEVICE. */
+int dugks_mass(const dugks_plan *plan, void *state, int64_t step,
+               double *mass_out_dev, void *stream);
+
+/* FP32 plans: measure the mass of the state at `step` as dugks_mass does and
+ * add w_i * (M0 - M) / (nx ny) to every f~_i, M0 being the mass of phi0 in
+ * FP64 recorded by dugks_init.  The correction's own rounding is measured and
+ * corrected once more.  FP64 plans: no-op.  Asynchronous. */
+int dugks_mass_correct(const dugks_plan *plan, void *state, int64_t step,
+                       void *stream);
+
+/* Initial mass M0 (FP64) recorded by dugks_init, copied to *out_dev. */
+int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
+                void *stream);
+
+const char *dugks_strerror(int status);
+
+/* Library version string. */
+const char *dugks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,167 @@
+"""ctypes binding of the C ABI in include/dugks.h: argument marshalling only.
+
+Every function keeps the C name; pointers are passed as integers (device
+addresses from torch tensors, hipStream_t handles from torch streams).  The
+library must be built (``paper_2007_07760_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libdugks.so")
+HEADER = os.path.join(ROOT, "include", "dugks.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = range(6)
+F64, F32 = 0, 1
+CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
+VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
+FLAG_DTPHIU_ZERO = 1
+
+
+class DugksError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {dugks_strerror(code)} (status {code})")
+
+
+class dugks_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("mobility", ctypes.c_double), ("width", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("recon", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("vel_kind", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("vel_param", ctypes.c_double * 6),
+        ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libdugks.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_2007_07760_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    P = ctypes.POINTER(dugks_params)
+    L.dugks_plan_create.argtypes = [P, ctypes.POINTER(vp)]
+    L.dugks_plan_destroy.argtypes = [vp]
+    L.dugks_plan_destroy.restype = None
+    L.dugks_state_bytes.argtypes = [vp]
+    L.dugks_state_bytes.restype = ctypes.c_size_t
+    L.dugks_init.argtypes = [vp, vp, vp, vp]
+    L.dugks_step.argtypes = [vp, vp, i64, i64, vp]
+    L.dugks_phi.argtypes = [vp, vp, i64, vp, vp]
+    L.dugks_mass.argtypes = [vp, vp, i64, vp, vp]
+    L.dugks_distributions.argtypes = [vp, vp, i64, vp, vp]
+    L.dugks_mass_correct.argtypes = [vp, vp, i64, vp]
+    L.dugks_mass0.argtypes = [vp, vp, vp, vp]
+    L.dugks_strerror.argtypes = [ctypes.c_int]
+    L.dugks_strerror.restype = ctypes.c_char_p
+    L.dugks_version.restype = ctypes.c_char_p
+    for name in ("dugks_plan_create", "dugks_init", "dugks_step", "dugks_phi",
+                 "dugks_distributions",
+                 "dugks_mass", "dugks_mass_correct", "dugks_mass0"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/dugks.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dugks_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise DugksError(rc, where)
+
+
+def make_params(nx, ny, mobility, width, cfl, recon=UPWIND3, precision=F64,
+                vel_kind=VEL_UNIFORM, vel_param=(0.0, 0.0), flags=0,
+                tile_rows=0) -> dugks_params:
+    p = dugks_params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.mobility, p.width, p.cfl = float(mobility), float(width), float(cfl)
+    p.recon, p.precision, p.vel_kind = int(recon), int(precision), int(vel_kind)
+    p.flags = int(flags)
+    vp = list(vel_param) + [0.0] * (6 - len(vel_param))
+    for k in range(6):
+        p.vel_param[k] = float(vp[k])
+    p.tile_rows = int(tile_rows)
+    p.reserved = 0
+    return p
+
+
+def dugks_plan_create(params: dugks_params) -> int:
+    out = ctypes.c_void_p()
+    _check(load().dugks_plan_create(ctypes.byref(params), ctypes.byref(out)),
+           "dugks_plan_create")
+    return out.value
+
+
+def dugks_plan_create_status(params) -> int:
+    """Status of plan creation for possibly-invalid params (no exception)."""
+    out = ctypes.c_void_p()
+    ptr = ctypes.byref(params) if params is not None else None
+    rc = load().dugks_plan_create(ptr, ctypes.byref(out))
+    if rc == OK:
+        load().dugks_plan_destroy(out)
+    return rc
+
+
+def dugks_plan_destroy(plan: int) -> None:
+    load().dugks_plan_destroy(plan)
+
+
+def dugks_state_bytes(plan: int) -> int:
+    return load().dugks_state_bytes(plan)
+
+
+def dugks_init(plan: int, state: int, phi0_dev: int, stream: int) -> None:
+    _check(load().dugks_init(plan, state, phi0_dev, stream), "dugks_init")
+
+
+def dugks_step(plan: int, state: int, step: int, nsteps: int, stream: int) -> None:
+    _check(load().dugks_step(plan, state, step, nsteps, stream), "dugks_step")
+
+
+def dugks_phi(plan: int, state: int, step: int, out_dev: int, stream: int) -> None:
+    _check(load().dugks_phi(plan, state, step, out_dev, stream), "dugks_phi")
+
+
+def dugks_distributions(plan: int, state: int, step: int, out_dev: int,
+                        stream: int) -> None:
+    _check(load().dugks_distributions(plan, state, step, out_dev, stream),
+           "dugks_distributions")
+
+
+def dugks_mass(plan: int, state: int, step: int, out_dev: int, stream: int) -> None:
+    _check(load().dugks_mass(plan, state, step, out_dev, stream), "dugks_mass")
+
+
+def dugks_mass_correct(plan: int, state: int, step: int, stream: int) -> None:
+    _check(load().dugks_mass_correct(plan, state, step, stream), "dugks_mass_correct")
+
+
+def dugks_mass0(plan: int, state: int, out_dev: int, stream: int) -> None:
+    _check(load().dugks_mass0(plan, state, out_dev, stream), "dugks_mass0")
+
+
+def dugks_strerror(code: int) -> str:
+    return load().dugks_strerror(code).decode()
+
+
+def dugks_version() -> str:
+    return load().dugks_version().decode()

@@ -1,0 +1,472 @@
+// dugks_abi.hip -- C ABI of the DUGKS library (include/dugks.h): plan
+// validation and set-up on the host, launches of the device kernels.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "dugks_common.h"
+#include "dugks_kernels.h"
+
+using namespace dugks;
+
+struct dugks_plan {
+  dugks_params p;
+  Layout L;
+  double coef[2][9][NTAP];   // face stencils (Eqs. 25-26)
+  double dt, h, tau;
+  double cA, cB, cA2, cB2, alpha, beta, gamma;
+  double period;             // cos(pi t / period) modulation; 0 = steady
+  int seg_rows, nstrips, nsegs;
+  std::vector<double> tabx, taby;
+};
+
+namespace {
+
+constexpr double RT = 1.0 / 3.0;
+
+bool finite(double v) { return isfinite(v); }
+
+// ------------------------------------------------------------ stencils
+// bf = sum over the patch of c * fbar+, for face orientation o and velocity i.
+void add_tap(double (&c)[NTAP], int o, int s, int q, double v) {
+  int dx = o == 0 ? s : q;
+  int dy = o == 0 ? q : s;
+  c[tap_index(o, dx, dy)] += v;
+}
+
+void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
+  memset(coef, 0, sizeof(coef));
+  for (int o = 0; o < 2; o++)
+    for (int i = 0; i < 9; i++) {
+      double(&c)[NTAP] = coef[o][i];
+      // velocity components along the face normal (n) and tangent (t)
+      const int en = o == 0 ? ex(i) : ey(i);
+      const int et = o == 0 ? ey(i) : ex(i);
+      if (recon == DUGKS_UPWIND3) {
+        // foot of the characteristic relative to the centre of L, (n, t)
+        const double pn = 0.5 - en * h, pt = -et * h;
+        auto side = [&](int ks, double wgt) {
+          // f(k) + d.G + (1/2) d.H.d with G = 3 sum w_m e_m f_m and
+          // H = 9 sum w_m (e_m e_m - I/3) f_m over the 3x3 patch about k
+          const double dn = pn - ks, dq = pt;
+          const double d2 = dn * dn + dq * dq;
+          add_tap(c, o, ks, 0, wgt);
+          for (int m = 0; m < 9; m++) {
+            // the lattice is symmetric under x <-> y, so e_m in (n, t) axes
+            const int mn = o == 0 ? ex(m) : ey(m);
+            const int mt = o == 0 ? ey(m) : ex(m);
+            const double de = dn * mn + dq * mt;
+            const double v = 3.0 * wq(m) * de + 4.5 * wq(m) * (de * de - d2 / 3.0);
+            add_tap(c, o, ks + mn, mt, wgt * v);
+          }
+        };
+        if (en > 0)
+          side(0, 1.0);
+        else if (en < 0)
+          side(1, 1.0);
+        else {
+          side(0, 0.5);
+          side(1, 0.5);
+        }
+      } else if (recon == DUGKS_CENTRAL2) {
+        // F = (fL + fR)/2, dn = fR - fL, dt = (fL+t + fR+t - fL-t - fR-t)/4,
+        // bf = F - h (en dn + et dt)
+        add_tap(c, o, 0, 0, 0.5);
+        add_tap(c, o, 1, 0, 0.5);
+        add_tap(c, o, 1, 0, -h * en);
+        add_tap(c, o, 0, 0, h * en);
+        const double q = -h * et * 0.25;
+        add_tap(c, o, 0, 1, q);
+        add_tap(c, o, 1, 1, q);
+        add_tap(c, o, 0, -1, -q);
+        add_tap(c, o, 1, -1, -q);
+      } else {
+        // fourth order on LL, L, R, RR (s = -1..2):
+        // F = (-1, 9, 9, -1)/16, dn = (1, -27, 27, -1)/24,
+        // dt = sum_s F_s D_s with D = (1, -8, 0, 8, -1)/12 across the tangent
+        const double wF[4] = {-1.0 / 16, 9.0 / 16, 9.0 / 16, -1.0 / 16};
+        const double wN[4] = {1.0 / 24, -27.0 / 24, 27.0 / 24, -1.0 / 24};
+        const double wD[5] = {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12};
+        for (int s = -1; s <= 2; s++) {
+          add_tap(c, o, s, 0, wF[s + 1]);
+          add_tap(c, o, s, 0, -h * en * wN[s + 1]);
+          if (et != 0)
+            for (int q = -2; q <= 2; q++)
+              if (q != 0) add_tap(c, o, s, q, -h * et * wF[s + 1] * wD[q + 2]);
+        }
+      }
+    }
+}
+
+// ------------------------------------------------------ velocity tables
+// u(x, y, t) = g(t) UX(x) UY(y), v = g(t) VX(x) VY(y), tables at x = k/2.
+void make_tables(dugks_plan* P) {
+  const dugks_params& p = P->p;
+  const int nx = p.nx, ny = p.ny;
+  const double* q = p.vel_param;
+  P->tabx.assign(2 * (2 * (size_t)nx + 2), 0.0);
+  P->taby.assign(2 * (2 * (size_t)ny + 2), 0.0);
+  double* UX = P->tabx.data();
+  double* VX = UX + (2 * nx + 2);
+  double* UY = P->taby.data();
+  double* VY = UY + (2 * ny + 2);
+  P->period = 0.0;
+  for (int k = 0; k < 2 * nx + 2; k++) {
+    const double x = 0.5 * k;
+    switch (p.vel_kind) {
+      case DUGKS_VEL_UNIFORM: UX[k] = 1.0; VX[k] = 1.0; break;
+      case DUGKS_VEL_ROTATION: UX[k] = 1.0; VX[k] = q[0] * (x - q[1]); break;
+      case DUGKS_VEL_SINGLE_VORTEX: {
+        const double s = sin(M_PI * (x / nx));
+        UX[k] = -q[0] * s * s;
+        VX[k] = q[0] * sin(2.0 * M_PI * (x / nx));
+        break;
+      }
+      case DUGKS_VEL_DEFORMATION: {
+        const double ax = 4.0 * M_PI * x / nx;
+        UX[k] = -q[0] * sin(ax);
+        VX[k] = -q[0] * cos(ax);
+        break;
+      }
+    }
+  }
+  for (int k = 0; k < 2 * ny + 2; k++) {
+    const double y = 0.5 * k;
+    switch (p.vel_kind) {
+      case DUGKS_VEL_UNIFORM: UY[k] = q[0]; VY[k] = q[1]; break;
+      case DUGKS_VEL_ROTATION: UY[k] = -q[0] * (y - q[2]); VY[k] = 1.0; break;
+      case DUGKS_VEL_SINGLE_VORTEX: {
+        const double s = sin(M_PI * (y / ny));
+        UY[k] = sin(2.0 * M_PI * (y / ny));
+        VY[k] = s * s;
+        break;
+      }
+      case DUGKS_VEL_DEFORMATION: {
+        const double ay = 4.0 * M_PI * y / ny;
+        UY[k] = sin(ay);
+        VY[k] = cos(ay);
+        break;
+      }
+    }
+  }
+  if (p.vel_kind == DUGKS_VEL_SINGLE_VORTEX || p.vel_kind == DUGKS_VEL_DEFORMATION)
+    P->period = q[1];
+  if (p.vel_kind == DUGKS_VEL_ROTATION) {
+    // the rotation is u = -w (y - yc): UX = 1 and the sign sits in UY
+  }
+}
+
+int validate(const dugks_params* p) {
+  if (!p) return DUGKS_EINVAL;
+  if (p->nx < 8 || p->ny < 8 || p->nx > 65536 || p->ny > 65536) return DUGKS_EINVAL;
+  if (!finite(p->mobility) || !(p->mobility > 0.0)) return DUGKS_EINVAL;
+  if (isnan(p->width) || !(p->width > 0.0)) return DUGKS_EINVAL;
+  if (!finite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0) return DUGKS_EINVAL;
+  if (p->recon < 0 || p->recon > 2) return DUGKS_EINVAL;
+  if (p->precision < 0 || p->precision > 1) return DUGKS_EINVAL;
+  if (p->vel_kind < 0 || p->vel_kind > 4) return DUGKS_EINVAL;
+  if (p->flags & ~DUGKS_FLAG_DTPHIU_ZERO) return DUGKS_EINVAL;
+  if (p->tile_rows < 0 || p->tile_rows > 65536 || p->reserved != 0) return DUGKS_EINVAL;
+  for (int k = 0; k < 6; k++)
+    if (!finite(p->vel_param[k])) return DUGKS_EINVAL;
+  if ((p->vel_kind == DUGKS_VEL_SINGLE_VORTEX || p->vel_kind == DUGKS_VEL_DEFORMATION) &&
+      !(p->vel_param[1] > 0.0))
+    return DUGKS_EINVAL;
+  if (p->vel_kind == DUGKS_VEL_ARRAYS) return DUGKS_EUNSUPPORTED;
+  return DUGKS_OK;
+}
+
+bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
+
+int hip_status(hipError_t e) { return e == hipSuccess ? DUGKS_OK : DUGKS_EDEVICE; }
+
+template <typename T>
+T* at(void* state, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(state) + off);
+}
+template <typename T>
+const T* at(const void* state, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(state) + off);
+}
+
+// ------------------------------------------------------------ launches
+template <typename T>
+StepBufs<T> step_bufs(const dugks_plan* P, void* state, int64_t n) {
+  const Layout& L = P->L;
+  const int b = (int)(n & 1);
+  StepBufs<T> q;
+  q.src = at<T>(state, L.off_tf[b]);
+  q.dst = at<T>(state, L.off_tf[b ^ 1]);
+  q.ph_src = at<T>(state, L.off_ph[b]);
+  q.ph_dst = at<T>(state, L.off_ph[b ^ 1]);
+  q.cf = at<T>(state, L.off_coef);
+  q.tabx = at<T>(state, L.off_tabx);
+  q.taby = at<T>(state, L.off_taby);
+  return q;
+}
+
+template <typename T>
+StepArgs<T> step_args(const dugks_plan* P) {
+  const Layout& L = P->L;
+  StepArgs<T> a;
+  a.pitch = L.pitch;
+  a.plane = L.plane;
+  a.nx = P->p.nx;
+  a.ny = P->p.ny;
+  a.seg_rows = P->seg_rows;
+  a.nstrips = P->nstrips;
+  a.nsegs = P->nsegs;
+  a.nlogical = P->nstrips * P->nsegs;
+  a.cA = T(P->cA);
+  a.cB = T(P->cB);
+  a.cA2 = T(P->cA2);
+  a.cB2 = T(P->cB2);
+  a.dalpha = T(P->dt * P->alpha);
+  a.dt = T(P->dt);
+  a.beta = T(P->beta);
+  a.gamma = T(P->gamma);
+  a.tau = T(P->tau);
+  a.kth = isfinite(P->p.width) ? T(4.0 / P->p.width) : T(0);
+  a.period = P->period;
+  a.dtd = P->dt;
+  a.hd = P->h;
+  a.jzero = (P->p.flags & DUGKS_FLAG_DTPHIU_ZERO) ? 1 : 0;
+  return a;
+}
+
+template <typename T>
+int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+  StepArgs<T> a = step_args<T>(P);
+  StepBufs<T> q = step_bufs<T>(P, state, n);
+  const int per = (a.nlogical + 7) / 8;
+  dim3 grid(per * 8), block(LANES);
+#define DUGKS_LAUNCH(RR)                                                                   \
+  hipLaunchKernelGGL((step_kernel<T, RR>), grid, block, 0, s, a, n, q.src, q.dst, q.ph_src, \
+                     q.ph_dst, q.cf, q.tabx, q.taby)
+  switch (P->p.recon) {
+    case DUGKS_CENTRAL2: DUGKS_LAUNCH(DUGKS_CENTRAL2); break;
+    case DUGKS_UPWIND3: DUGKS_LAUNCH(DUGKS_UPWIND3); break;
+    default: DUGKS_LAUNCH(DUGKS_CENTRAL4); break;
+  }
+#undef DUGKS_LAUNCH
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
+int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s) {
+  const Layout& L = P->L;
+  const int nx = P->p.nx, ny = P->p.ny;
+  // header, coefficients and velocity tables in the state's precision
+  StateHeader h;
+  memset(&h, 0, sizeof(h));
+  h.magic = STATE_MAGIC;
+  h.nx = nx;
+  h.ny = ny;
+  h.precision = P->p.precision;
+  h.recon = P->p.recon;
+  std::vector<T> cf(2 * 9 * NTAP), tx(P->tabx.size()), ty(P->taby.size());
+  for (int o = 0; o < 2; o++)
+    for (int i = 0; i < 9; i++)
+      for (int t = 0; t < NTAP; t++) cf[(o * 9 + i) * NTAP + t] = T(P->coef[o][i][t]);
+  for (size_t k = 0; k < tx.size(); k++) tx[k] = T(P->tabx[k]);
+  for (size_t k = 0; k < ty.size(); k++) ty[k] = T(P->taby[k]);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(state, &h, sizeof(h), hipMemcpyHostToDevice, s))) return hip_status(e);
+  if ((e = hipMemcpyAsync(at<T>(state, L.off_coef), cf.data(), cf.size() * sizeof(T),
+                          hipMemcpyHostToDevice, s)))
+    return hip_status(e);
+  if ((e = hipMemcpyAsync(at<T>(state, L.off_tabx), tx.data(), tx.size() * sizeof(T),
+                          hipMemcpyHostToDevice, s)))
+    return hip_status(e);
+  if ((e = hipMemcpyAsync(at<T>(state, L.off_taby), ty.data(), ty.size() * sizeof(T),
+                          hipMemcpyHostToDevice, s)))
+    return hip_status(e);
+  InitArgs<T> a;
+  a.phi0 = phi0;
+  a.tf = at<T>(state, L.off_tf[0]);
+  a.ph = at<T>(state, L.off_ph[0]);
+  a.tabx = at<T>(state, L.off_tabx);
+  a.taby = at<T>(state, L.off_taby);
+  a.pitch = L.pitch;
+  a.plane = L.plane;
+  a.nx = nx;
+  a.ny = ny;
+  a.dt = P->dt;
+  a.kth = isfinite(P->p.width) ? 4.0 / P->p.width : 0.0;
+  dim3 grid((nx + 255) / 256, ny), block(256);
+  hipLaunchKernelGGL((init_kernel<T>), grid, block, 0, s, a);
+  if ((e = hipGetLastError())) return hip_status(e);
+  // M0: FP64 total of phi0 itself (not of its rounded f~)
+  double* part = at<double>(state, L.off_scratch);
+  StateHeader* hd = at<StateHeader>(state, 0);
+  hipLaunchKernelGGL((mass_partial_kernel<double, 1>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
+                     phi0, (int64_t)nx, (int64_t)0, nx, ny, part);
+  hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass0,
+                     &hd->mass_now);
+  if ((e = hipGetLastError())) return hip_status(e);
+  // the host staging vectors must outlive the copies
+  return hip_status(hipStreamSynchronize(s));
+}
+
+template <typename T>
+int do_phi(const dugks_plan* P, const void* state, int64_t n, void* out, hipStream_t s) {
+  const Layout& L = P->L;
+  const int nx = P->p.nx, ny = P->p.ny;
+  dim3 grid((nx + 255) / 256, ny), block(256);
+  hipLaunchKernelGGL((phi_kernel<T>), grid, block, 0, s, at<T>(state, L.off_tf[n & 1]),
+                     L.pitch, L.plane, nx, ny, static_cast<T*>(out));
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
+int do_export(const dugks_plan* P, const void* state, int64_t n, void* out, hipStream_t s) {
+  const Layout& L = P->L;
+  const int nx = P->p.nx, ny = P->p.ny;
+  dim3 grid((nx + 255) / 256, ny, 9), block(256);
+  hipLaunchKernelGGL((export_kernel<T>), grid, block, 0, s, at<T>(state, L.off_tf[n & 1]),
+                     L.pitch, L.plane, nx, ny, static_cast<T*>(out));
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
+int do_mass(const dugks_plan* P, void* state, int64_t n, double* out, hipStream_t s) {
+  const Layout& L = P->L;
+  double* part = at<double>(state, L.off_scratch);
+  StateHeader* hd = at<StateHeader>(state, 0);
+  hipLaunchKernelGGL((mass_partial_kernel<T, 9>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
+                     at<T>(state, L.off_tf[n & 1]), L.pitch, L.plane, P->p.nx, P->p.ny, part);
+  hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass_now, out);
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
+int do_correct(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+  const Layout& L = P->L;
+  const int nx = P->p.nx, ny = P->p.ny;
+  const StateHeader* hd = at<StateHeader>(state, 0);
+  dim3 grid((nx + 255) / 256, ny), block(256);
+  for (int pass = 0; pass < 2; pass++) {
+    int rc = do_mass<T>(P, state, n, nullptr, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL((mass_correct_kernel<T>), grid, block, 0, s,
+                       at<T>(state, L.off_tf[n & 1]), L.pitch, L.plane, nx, ny, hd);
+    if (hipGetLastError() != hipSuccess) return DUGKS_EDEVICE;
+  }
+  return DUGKS_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
+  if (!out) return DUGKS_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  dugks_plan* P = new (std::nothrow) dugks_plan();
+  if (!P) return DUGKS_ENOMEM;
+  P->p = *p;
+  P->L = make_layout(p->nx, p->ny, p->precision);
+  P->dt = p->cfl;                 // Eq. (39), dx = sqrt(3RT) = 1
+  P->h = 0.5 * P->dt;
+  P->tau = p->mobility / RT;      // M_phi = tau RT
+  const double tau = P->tau, dt = P->dt, h = P->h;
+  // g+ = (tau - b)/(tau + a) g + (a + b)/(tau + a) (feq + tau S) for
+  // g = f - a (Omega + S), g+ = f + b (Omega + S)
+  P->cA = (2 * tau - dt) / (2 * tau + dt);     // (a, b) = (dt/2, dt/2): f~+
+  P->cB = 2 * dt / (2 * tau + dt);
+  P->cA2 = (2 * tau - h) / (2 * tau + dt);     // (a, b) = (dt/2, h/2): fbar+
+  P->cB2 = 3 * h / (2 * tau + dt);
+  P->alpha = 2 * tau / (2 * tau + h);          // Eq. (27)
+  P->beta = h / (2 * tau + h);
+  P->gamma = tau * h / (2 * tau + h);
+  make_coefficients(p->recon, h, P->coef);
+  make_tables(P);
+  P->seg_rows = p->tile_rows > 0 ? p->tile_rows : 64;
+  if (P->seg_rows > p->ny) P->seg_rows = p->ny;
+  P->nstrips = (p->nx + OWN - 1) / OWN;
+  P->nsegs = (p->ny + P->seg_rows - 1) / P->seg_rows;
+  *out = P;
+  return DUGKS_OK;
+}
+
+void dugks_plan_destroy(dugks_plan* plan) { delete plan; }
+
+size_t dugks_state_bytes(const dugks_plan* plan) { return plan ? plan->L.total : 0; }
+
+int dugks_init(const dugks_plan* plan, void* state, const double* phi0_dev, void* stream) {
+  if (!plan || !state || !phi0_dev || !aligned(state)) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->p.precision == DUGKS_F64 ? do_init<double>(plan, state, phi0_dev, s)
+                                        : do_init<float>(plan, state, phi0_dev, s);
+}
+
+int dugks_step(const dugks_plan* plan, void* state, int64_t step, int64_t nsteps,
+               void* stream) {
+  if (!plan || !state || !aligned(state) || step < 0 || nsteps < 0) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int64_t k = 0; k < nsteps; k++) {
+    int rc = plan->p.precision == DUGKS_F64 ? launch_step<double>(plan, state, step + k, s)
+                                            : launch_step<float>(plan, state, step + k, s);
+    if (rc) return rc;
+  }
+  return DUGKS_OK;
+}
+
+int dugks_phi(const dugks_plan* plan, const void* state, int64_t step, void* phi_out_dev,
+              void* stream) {
+  if (!plan || !state || !phi_out_dev || !aligned(state) || step < 0) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->p.precision == DUGKS_F64 ? do_phi<double>(plan, state, step, phi_out_dev, s)
+                                        : do_phi<float>(plan, state, step, phi_out_dev, s);
+}
+
+int dugks_distributions(const dugks_plan* plan, const void* state, int64_t step,
+                        void* out_dev, void* stream) {
+  if (!plan || !state || !out_dev || !aligned(state) || step < 0) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->p.precision == DUGKS_F64 ? do_export<double>(plan, state, step, out_dev, s)
+                                        : do_export<float>(plan, state, step, out_dev, s);
+}
+
+int dugks_mass(const dugks_plan* plan, void* state, int64_t step, double* mass_out_dev,
+               void* stream) {
+  if (!plan || !state || !mass_out_dev || !aligned(state) || step < 0) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->p.precision == DUGKS_F64 ? do_mass<double>(plan, state, step, mass_out_dev, s)
+                                        : do_mass<float>(plan, state, step, mass_out_dev, s);
+}
+
+int dugks_mass_correct(const dugks_plan* plan, void* state, int64_t step, void* stream) {
+  if (!plan || !state || !aligned(state) || step < 0) return DUGKS_EINVAL;
+  if (plan->p.precision == DUGKS_F64) return DUGKS_OK;
+  return do_correct<float>(plan, state, step, static_cast<hipStream_t>(stream));
+}
+
+int dugks_mass0(const dugks_plan* plan, const void* state, double* out_dev, void* stream) {
+  if (!plan || !state || !out_dev || !aligned(state)) return DUGKS_EINVAL;
+  const StateHeader* hd = at<StateHeader>(state, 0);
+  return hip_status(hipMemcpyAsync(out_dev, &hd->mass0, sizeof(double),
+                                   hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+}
+
+const char* dugks_strerror(int status) {
+  switch (status) {
+    case DUGKS_OK: return "ok";
+    case DUGKS_EINVAL: return "invalid argument";
+    case DUGKS_ENOMEM: return "out of host memory";
+    case DUGKS_EDEVICE: return "HIP launch or runtime call failed";
+    case DUGKS_ENUMERIC: return "non-finite total mass";
+    case DUGKS_EUNSUPPORTED: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+const char* dugks_version(void) { return "dugks-gfx950 0.1"; }
+
+}  // extern "C"

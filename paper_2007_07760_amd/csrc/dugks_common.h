@@ -1,0 +1,120 @@
+// dugks_common.h -- constants, stencil geometry and state layout shared by
+// the host and device code of the library (not by the oracle).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "dugks.h"
+
+namespace dugks {
+
+// ------------------------------------------------------------- D2Q9 lattice
+// Paper order (Sec. II.B.2): rest, E, NE, N, NW, W, SW, S, SE; xi_i = e_i
+// because sqrt(3RT) = 1 with RT = 1/3.
+__host__ __device__ constexpr int ex(int i) {
+  return (i == 1 || i == 2 || i == 8) ? 1 : ((i == 4 || i == 5 || i == 6) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int i) {
+  return (i == 2 || i == 3 || i == 4) ? 1 : ((i == 6 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr double wq(int i) {
+  return i == 0 ? 4.0 / 9.0 : ((i & 1) ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+// ------------------------------------------------------ stencil geometry
+// Face reconstruction bf_i = sum_t c[o][i][t] * fbar+_i(L + (dx_t, dy_t)),
+// with L the cell on the low side of the face.  o = 0: east face of L (normal
+// +x); o = 1: north face of L (normal +y).  Patch of offsets per orientation:
+//   o = 0: dx in [-1, 2], dy in [-2, 2]      o = 1: dx in [-2, 2], dy in [-1, 2]
+constexpr int NTAP = 20;
+__host__ __device__ constexpr int tap_dx(int o, int t) { return o == 0 ? (t % 4) - 1 : (t % 5) - 2; }
+__host__ __device__ constexpr int tap_dy(int o, int t) { return o == 0 ? (t / 4) - 2 : (t / 5) - 1; }
+__host__ __device__ constexpr int tap_index(int o, int dx, int dy) {
+  return o == 0 ? (dy + 2) * 4 + (dx + 1) : (dy + 1) * 5 + (dx + 2);
+}
+
+// Which taps a reconstruction uses (compile-time in the kernels).  s = offset
+// along the face normal, t = offset along the tangent, both from L.
+__host__ __device__ constexpr bool tap_used(int recon, int o, int i, int t) {
+  int dx = tap_dx(o, t), dy = tap_dy(o, t);
+  int s = o == 0 ? dx : dy;
+  int q = o == 0 ? dy : dx;
+  int en = o == 0 ? ex(i) : ey(i);
+  int et = o == 0 ? ey(i) : ex(i);
+  if (recon == DUGKS_UPWIND3) {
+    int lo = en < 0 ? 0 : -1;   // upstream cell L (s=0) or R (s=1), 3x3 about it
+    int hi = en > 0 ? 1 : 2;
+    return s >= lo && s <= hi && q >= -1 && q <= 1;
+  }
+  if (recon == DUGKS_CENTRAL2)
+    return (s == 0 || s == 1) && (q == 0 || (et != 0 && (q == 1 || q == -1)));
+  // CENTRAL4
+  return s >= -1 && s <= 2 && (q == 0 || et != 0);
+}
+
+// ------------------------------------------------------------- march tiles
+// One wavefront owns a strip of OWN columns and marches up a segment of rows.
+// Its 64 lanes hold columns x0-3 .. x0+60: 3 halo columns each side.
+constexpr int LANES = 64;
+constexpr int HALO = 3;
+constexpr int OWN = LANES - 2 * HALO;
+constexpr int LPAD = 2;                 // LDS row padding each side
+constexpr int LROW = LANES + 2 * LPAD;  // LDS row length (elements)
+
+// ------------------------------------------------------------- state layout
+// [header 256 B][coef table][x tables][y tables][tf A][tf B][phi A][phi B][scratch]
+struct StateHeader {
+  uint64_t magic;
+  double mass0;        // FP64 total of phi0
+  double mass_now;     // last measured total
+  double delta;        // last correction per cell
+  int32_t nx, ny, precision, recon;
+  int64_t pad[26];
+};
+static_assert(sizeof(StateHeader) == 256, "header size");
+constexpr uint64_t STATE_MAGIC = 0x53474B5547554431ull;  // "1DUGUKGS"
+
+constexpr int MASS_BLOCKS = 256;   // fixed partial count: deterministic order
+constexpr int MASS_THREADS = 256;
+
+struct Layout {
+  size_t esize;        // bytes per element (8 or 4)
+  int64_t pitch;       // elements per row
+  int64_t plane;       // elements per plane (padded)
+  size_t off_coef, off_tabx, off_taby, off_tf[2], off_ph[2], off_scratch, total;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline Layout make_layout(int nx, int ny, int precision) {
+  Layout L;
+  L.esize = precision == DUGKS_F64 ? 8 : 4;
+  int64_t row_align = 256 / (int64_t)L.esize;
+  L.pitch = (int64_t)align_up((size_t)nx, (size_t)row_align);
+  // planes padded by one extra 2 KB stretch so the 9 planes do not alias in
+  // the HBM channel hash at power-of-two sizes
+  L.plane = L.pitch * ny + 2048 / (int64_t)L.esize;
+  size_t off = sizeof(StateHeader);
+  L.off_coef = off;
+  off = align_up(off + 2 * 9 * NTAP * L.esize, 256);
+  L.off_tabx = off;
+  off = align_up(off + 2 * (2 * (size_t)nx + 2) * L.esize, 256);
+  L.off_taby = off;
+  off = align_up(off + 2 * (2 * (size_t)ny + 2) * L.esize, 256);
+  for (int b = 0; b < 2; b++) {
+    L.off_tf[b] = off;
+    off = align_up(off + 9 * (size_t)L.plane * L.esize, 256);
+  }
+  for (int b = 0; b < 2; b++) {
+    L.off_ph[b] = off;
+    off = align_up(off + (size_t)L.plane * L.esize, 256);
+  }
+  L.off_scratch = off;
+  off = align_up(off + 2 * MASS_BLOCKS * sizeof(double) + 64, 256);
+  L.total = off;
+  return L;
+}
+
+}  // namespace dugks

@@ -1,0 +1,88 @@
+"""One grid advanced by the HIP library, with torch providing device memory and
+streams.  Every step of the scheme runs in libdugks.so; this class only
+allocates the state, keeps the step counter and marshals pointers."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+
+class Solver:
+    """A D2Q9 DUGKS solve of the conservative Allen-Cahn equation on one
+    periodic nx x ny grid (see include/dugks.h for the parameters)."""
+
+    def __init__(self, nx, ny, mobility, width, cfl, recon=C.UPWIND3,
+                 precision=C.F64, vel_kind=C.VEL_UNIFORM, vel_param=(0.0, 0.0),
+                 flags=0, tile_rows=0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a HIP device (no CPU path exists)")
+        self.params = C.make_params(nx, ny, mobility, width, cfl, recon, precision,
+                                    vel_kind, vel_param, flags, tile_rows)
+        self.nx, self.ny = int(nx), int(ny)
+        self.precision = int(precision)
+        self.dtype = torch.float64 if precision == C.F64 else torch.float32
+        self.plan = C.dugks_plan_create(self.params)
+        self.device = torch.device(device)
+        self.state = torch.empty(C.dugks_state_bytes(self.plan), dtype=torch.uint8,
+                                 device=self.device)
+        self.step_index = 0
+        self._scalar = torch.empty(1, dtype=torch.float64, device=self.device)
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan:
+            C.dugks_plan_destroy(plan)
+            self.plan = None
+
+    @staticmethod
+    def stream() -> int:
+        return torch.cuda.current_stream().cuda_stream
+
+    def init(self, phi0) -> "Solver":
+        phi0 = torch.as_tensor(np.ascontiguousarray(phi0, dtype=np.float64)
+                               if isinstance(phi0, np.ndarray) else phi0)
+        phi0 = phi0.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(phi0.shape) == (self.ny, self.nx)
+        C.dugks_init(self.plan, self.state.data_ptr(), phi0.data_ptr(), self.stream())
+        self.step_index = 0
+        return self
+
+    def step(self, nsteps: int = 1) -> "Solver":
+        C.dugks_step(self.plan, self.state.data_ptr(), self.step_index, nsteps,
+                     self.stream())
+        self.step_index += nsteps
+        return self
+
+    def phi(self) -> torch.Tensor:
+        out = torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+        C.dugks_phi(self.plan, self.state.data_ptr(), self.step_index, out.data_ptr(),
+                    self.stream())
+        return out
+
+    def distributions(self) -> torch.Tensor:
+        out = torch.empty((9, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        C.dugks_distributions(self.plan, self.state.data_ptr(), self.step_index,
+                              out.data_ptr(), self.stream())
+        return out
+
+    def mass(self) -> float:
+        C.dugks_mass(self.plan, self.state.data_ptr(), self.step_index,
+                     self._scalar.data_ptr(), self.stream())
+        m = float(self._scalar.item())
+        if not math.isfinite(m):
+            raise C.DugksError(C.ENUMERIC, "Solver.mass")
+        return m
+
+    def mass0(self) -> float:
+        C.dugks_mass0(self.plan, self.state.data_ptr(), self._scalar.data_ptr(),
+                      self.stream())
+        return float(self._scalar.item())
+
+    def mass_correct(self) -> "Solver":
+        C.dugks_mass_correct(self.plan, self.state.data_ptr(), self.step_index,
+                             self.stream())
+        return self
