@@ -1,0 +1,222 @@
+"""Throughput of the fused DUGKS step on one MI355X.
+
+Workload (the headline configuration): one D2Q9 DUGKS T2 step of the
+conservative Allen-Cahn equation on a 4096 x 4096 periodic grid, upwind-3
+(third-order isotropic) reconstruction, W = 4, M = 0.01, C = 0.5, 64 random
+tanh circles (R 20-200 cells, seed 0) in rigid rotation (corner speed 0.05).
+State is resident in HBM before the timed region; the timed region is exactly
+--steps calls of the step (one fused kernel each).  FP64 is the headline line;
+the FP32 form (with its FP64 mass correction every --mass-every steps) is
+reported in the same line.
+
+MLUPS = nx * ny * steps / time / 1e6.  Algorithmic traffic per lattice update:
+f~^n in and f~^{n+1} out (9 + 9 words), phi^{n-1} in and phi^n out (2 words):
+160 B in FP64, 80 B in FP32.  Peak HBM bandwidth of MI355X: 8 TB/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+WORDS_PER_LU = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--mass-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["f64", "f32"], default=None,
+                    help="time one precision only (profiling runs)")
+    return ap.parse_args()
+
+
+def time_steps(solver, steps, warmup, mass_every=0):
+    """Warm up, then time exactly `steps` steps with HIP events on the stream
+    the kernels run on; returns (seconds, mean kernel-region ms per step)."""
+    import torch
+    for k in range(warmup):
+        solver.step(1)
+        if mass_every and (k + 1) % mass_every == 0:
+            solver.mass_correct()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(steps):
+        solver.step(1)
+        if mass_every and (k + 1) % mass_every == 0:
+            solver.mass_correct()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = start.elapsed_time(stop)
+    return wall, ev_ms
+
+
+def time_kernel_only(solver, steps):
+    """Mean duration of the fused step kernel alone (HIP events around a run
+    of back-to-back launches on the same stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    solver.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def copy_bandwidth():
+    """Achievable device copy bandwidth (read + write bytes / time), GB/s."""
+    import torch
+    n = 1 << 28   # 2 GiB of float64 each side
+    a = torch.empty(n // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def profile_traffic(kernel_prefix: str, precision: str):
+    """HBM bytes per launch of the step kernel from a committed rocprofv3 PMC
+    summary (profiles/traffic_<precision>.json), if it matches this build."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"traffic_h1_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        from paper_2007_07760_amd import kernel_fingerprint
+        if rec.get("kernel_fingerprint") != kernel_fingerprint():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(w):
+    """The FP64 oracle as it stands, on this host's cores, on a bounded sample of
+    the same workload: its first step on the full 4096^2 grid."""
+    import oracle
+    p = oracle.Params(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                      w["recon"], w["vel_kind"], w["vel_param"])
+    s = oracle.State(p, w["phi0"])
+    t0 = time.perf_counter()
+    s.run(1)
+    dt = time.perf_counter() - t0
+    return {"value": w["nx"] * w["ny"] / dt / 1e6, "unit": "MLUPS",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"1 step (n=0) of the {w['nx']}x{w['ny']} workload, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    from paper_2007_07760_amd import inputs as I
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd.solver import Solver
+
+    w = I.workload("h1")
+    n = args.size
+    if n != w["nx"]:
+        w = dict(w, nx=n, ny=n, phi0=I.random_circles(n, n, 64, 20.0 * n / 4096,
+                                                      200.0 * n / 4096, 4.0, 0))
+    lus = w["nx"] * w["ny"]
+    results = {}
+    for prec_name, prec in (("f64", C.F64), ("f32", C.F32)):
+        if args.only and args.only != prec_name:
+            continue
+        s = Solver(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                   recon=w["recon"], precision=prec, vel_kind=w["vel_kind"],
+                   vel_param=w["vel_param"], tile_rows=args.tile_rows).init(w["phi0"])
+        me = args.mass_every if prec == C.F32 else 0
+        wall, ev_ms = time_steps(s, args.steps, args.warmup, me)
+        k_ms = time_kernel_only(s, min(args.steps, 50))
+        esize = 8 if prec == C.F64 else 4
+        alg_bytes = WORDS_PER_LU * esize * lus
+        achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+        results[prec_name] = dict(
+            wall=wall, ev_ms=ev_ms, kernel_ms=k_ms, achieved=achieved,
+            mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6,
+            traffic=profile_traffic("step_kernel", prec_name))
+        del s
+        torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth()
+    head = "f64" if "f64" in results else "f32"
+    r = results[head]
+    line = {
+        "metric": "MLUPS (DUGKS D2Q9 step, FP64 and FP32) and % HBM roofline",
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ev_ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": f"h1: {w['nx']}x{w['ny']} periodic D2Q9 DUGKS T2 step, "
+                               "upwind-3 isotropic reconstruction, W=4, M=0.01, C=0.5, "
+                               "64 tanh circles in rigid rotation",
+                   "nx": w["nx"], "ny": w["ny"], "recon": "upwind3",
+                   "tile_rows": args.tile_rows or "default"},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": r["traffic"],
+                     "kernel": "step_kernel (fused reconstruction + flux + update)",
+                     "kernel_ms": round(r["kernel_ms"], 4),
+                     "bytes_per_lu": WORDS_PER_LU * (8 if head == "f64" else 4)},
+        "copy_bandwidth_gbs": round(copy_gbs, 1),
+    }
+    if "f32" in results and head != "f32":
+        f = results["f32"]
+        line["fp32"] = {"value": round(f["mlups"], 1), "unit": "MLUPS",
+                        "ms_per_step": round(f["ev_ms"] / args.steps, 4),
+                        "mass_correction_every": args.mass_every,
+                        "kernel_ms": round(f["kernel_ms"], 4),
+                        "achieved": round(f["achieved"], 1),
+                        "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
+                        "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -19,22 +19,37 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dugks_oracle.c")
-_LIB = os.path.join(_HERE, "libdugks_oracle.so")
+# "plain": every expression rounded as written (-ffp-contract=off): the oracle.
+# "fma": the same source with a*b+c contracted to fused multiply-adds.  It is
+# not a reference for values; it is another rounding of the identical
+# arithmetic, used to measure how far rounding alone moves the method (the
+# normal grad(phi)/|grad(phi)| is ill-conditioned where the gradient vanishes
+# and theta does not).
+_LIBS = {"plain": os.path.join(_HERE, "libdugks_oracle.so"),
+         "fma": os.path.join(_HERE, "libdugks_oracle_fma.so")}
+_FLAGS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]}
+_LIB = _LIBS["plain"]
 
 CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (OpenMP over rows) into libdugks_oracle.so."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c11",
+def build(force: bool = False, variant: str = "plain") -> str:
+    """Compile the oracle with gcc (OpenMP over rows) into its shared object."""
+    out = _LIBS[variant]
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", *_FLAGS[variant], "-fopenmp", "-std=c11",
                "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-shared", "-fPIC",
                _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def build_all(force: bool = False) -> None:
+    for v in _LIBS:
+        build(force, v)
 
 
 class _Params(ctypes.Structure):
@@ -49,14 +64,12 @@ class _Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs: dict = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+def lib(variant: str = "plain"):
+    if variant not in _libs:
+        L = ctypes.CDLL(build(variant=variant))
         P = ctypes.POINTER(_Params)
         dp = ctypes.c_void_p
         L.oracle_step.argtypes = [P, ctypes.c_long, dp, dp, dp, dp]
@@ -76,8 +89,8 @@ def lib():
         L.oracle_aux_shift.argtypes = [ctypes.c_double] * 6
         L.oracle_aux_shift.restype = ctypes.c_double
         L.oracle_threads.restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -121,8 +134,9 @@ class Params:
 class State:
     """f~ (9 planes) and the phi history plane of one grid, FP64, on the host."""
 
-    def __init__(self, params: Params, phi0: np.ndarray):
+    def __init__(self, params: Params, phi0: np.ndarray, variant: str = "plain"):
         self.p = params
+        self.variant = variant
         self.cp = params.c()
         ny, nx = params.ny, params.nx
         phi0 = np.ascontiguousarray(phi0, dtype=np.float64)
@@ -130,12 +144,12 @@ class State:
         self.tf = np.empty((9, ny, nx))
         self.phi_hist = np.empty((ny, nx))
         self.step_index = 0
-        rc = lib().oracle_init(ctypes.byref(self.cp), _ptr(phi0), _ptr(self.tf),
+        rc = lib(variant).oracle_init(ctypes.byref(self.cp), _ptr(phi0), _ptr(self.tf),
                                _ptr(self.phi_hist))
         assert rc == 0
 
     def run(self, nsteps: int) -> "State":
-        rc = lib().oracle_run(ctypes.byref(self.cp), self.step_index, nsteps,
+        rc = lib(self.variant).oracle_run(ctypes.byref(self.cp), self.step_index, nsteps,
                               _ptr(self.tf), _ptr(self.phi_hist))
         if rc != 0:
             raise MemoryError("oracle_run failed")

@@ -7,3 +7,17 @@ with torch-owned device memory and streams.
 from . import _lib  # noqa: F401
 
 __all__ = ["_lib", "build", "inputs", "solver"]
+
+
+def kernel_fingerprint() -> str:
+    """Hash of the device sources; profile summaries record it so a counter
+    measurement is only reused for the kernel it was taken on."""
+    import hashlib
+    import os
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
