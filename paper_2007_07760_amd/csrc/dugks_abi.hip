@@ -16,6 +16,7 @@ struct dugks_plan {
   dugks_params p;
   Layout L;
   double coef[2][9][NTAP];   // face stencils (Eqs. 25-26)
+  double compact[NCOMPACT];  // the same, folded by the lattice symmetries
   double dt, h, tau;
   double cA, cB, cA2, cB2, alpha, beta, gamma;
   double period;             // cos(pi t / period) modulation; 0 = steady
@@ -99,6 +100,30 @@ void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
         }
       }
     }
+}
+
+// Fold the full table into the compact one (see compact_index): each entry is
+// taken from the east face (o = 0) of the velocity with e = (|en|, |et|), and
+// every (o, i, tap) used by the scheme must map onto it with the right sign.
+// Returns false if some coefficient is not reproduced (a broken symmetry).
+bool make_compact(int recon, const double (&coef)[2][9][NTAP], double (&cp)[NCOMPACT]) {
+  for (int k = 0; k < NCOMPACT; k++) cp[k] = 0.0;
+  const int rep[4] = {0, 3, 1, 2};   // class 2|en|+|et| -> velocity (|en|, |et|)
+  for (int c = 0; c < 4; c++)
+    for (int t = 0; t < NTAP; t++)
+      if (tap_used(recon, 0, rep[c], t)) cp[compact_index(0, rep[c], t)] = coef[0][rep[c]][t];
+  for (int o = 0; o < 2; o++)
+    for (int i = 0; i < 9; i++)
+      for (int t = 0; t < NTAP; t++) {
+        const double want = coef[o][i][t];
+        if (!tap_used(recon, o, i, t)) {
+          if (want != 0.0) return false;
+          continue;
+        }
+        const double got = cp[compact_index(o, i, t)];
+        if (fabs(got - want) > 1e-14 * (1.0 + fabs(want))) return false;
+      }
+  return true;
 }
 
 // ------------------------------------------------------ velocity tables
@@ -267,10 +292,8 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   h.ny = ny;
   h.precision = P->p.precision;
   h.recon = P->p.recon;
-  std::vector<T> cf(2 * 9 * NTAP), tx(P->tabx.size()), ty(P->taby.size());
-  for (int o = 0; o < 2; o++)
-    for (int i = 0; i < 9; i++)
-      for (int t = 0; t < NTAP; t++) cf[(o * 9 + i) * NTAP + t] = T(P->coef[o][i][t]);
+  std::vector<T> cf(NCOMPACT), tx(P->tabx.size()), ty(P->taby.size());
+  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->compact[k]);
   for (size_t k = 0; k < tx.size(); k++) tx[k] = T(P->tabx[k]);
   for (size_t k = 0; k < ty.size(); k++) ty[k] = T(P->taby[k]);
   hipError_t e;
@@ -386,6 +409,10 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
   P->beta = h / (2 * tau + h);
   P->gamma = tau * h / (2 * tau + h);
   make_coefficients(p->recon, h, P->coef);
+  if (!make_compact(p->recon, P->coef, P->compact)) {
+    delete P;
+    return DUGKS_EINVAL;   // cannot happen for the schemes built in
+  }
   make_tables(P);
   P->seg_rows = p->tile_rows > 0 ? p->tile_rows : 64;
   if (P->seg_rows > p->ny) P->seg_rows = p->ny;

@@ -54,6 +54,40 @@ __host__ __device__ constexpr bool tap_used(int recon, int o, int i, int t) {
   return s >= -1 && s <= 2 && (q == 0 || et != 0);
 }
 
+// ------------------------------------------------ compact coefficient table
+// The stencil of (orientation o, velocity i) depends only on the velocity's
+// components along the face normal and tangent, en = e_i.n and et = e_i.t, and
+// the lattice's mirror symmetries relate the signs: mirroring across the face
+// (s -> 1 - s) maps en -> -en, mirroring across the normal (q -> -q) maps
+// et -> -et.  So four classes (|en|, |et|) hold every coefficient, in canonical
+// tap coordinates s' = (en < 0 ? 1 - s : s), q' = (et < 0 ? -q : q), further
+// folded where a class is symmetric: q' -> |q'| when et = 0 (even in q) and
+// s' -> min(s', 1 - s') when en = 0 (even about the face).  The mirrors are
+// exact symmetries of every scheme here, so no entry changes sign.
+//
+// Compact layout: class c = 2|en| + |et|, entry (s', q') at
+//   cbase(c) + (s' + 1) * 5 + (q' + 2),   s' in [-1, 2], q' in [-2, 2].
+constexpr int CCLASS = 20;            // entries per class
+constexpr int NCOMPACT = 4 * CCLASS;  // 80 slots, at most ~48 used
+__host__ __device__ constexpr int cls_of(int en, int et) {
+  return 2 * (en < 0 ? -en : en) + (et < 0 ? -et : et);
+}
+__host__ __device__ constexpr int canon_s(int en, int s) {
+  return en < 0 ? 1 - s : (en == 0 ? (s < 1 - s ? s : 1 - s) : s);
+}
+__host__ __device__ constexpr int canon_q(int et, int q) {
+  return et < 0 ? -q : (et == 0 ? (q < 0 ? -q : q) : q);
+}
+// compact index of tap t of (o, i)
+__host__ __device__ constexpr int compact_index(int o, int i, int t) {
+  int dx = tap_dx(o, t), dy = tap_dy(o, t);
+  int s = o == 0 ? dx : dy;
+  int q = o == 0 ? dy : dx;
+  int en = o == 0 ? ex(i) : ey(i);
+  int et = o == 0 ? ey(i) : ex(i);
+  return cls_of(en, et) * CCLASS + (canon_s(en, s) + 1) * 5 + (canon_q(et, q) + 2);
+}
+
 // ------------------------------------------------------------- march tiles
 // One wavefront owns a strip of OWN columns and marches up a segment of rows.
 // Its 64 lanes hold columns x0-3 .. x0+60: 3 halo columns each side.
@@ -98,7 +132,7 @@ inline Layout make_layout(int nx, int ny, int precision) {
   L.plane = L.pitch * ny + 2048 / (int64_t)L.esize;
   size_t off = sizeof(StateHeader);
   L.off_coef = off;
-  off = align_up(off + 2 * 9 * NTAP * L.esize, 256);
+  off = align_up(off + NCOMPACT * L.esize, 256);
   L.off_tabx = off;
   off = align_up(off + 2 * (2 * (size_t)nx + 2) * L.esize, 256);
   L.off_taby = off;

@@ -40,29 +40,32 @@ struct StepArgs {
 };
 
 template <typename T>
+struct StepBufs {
+  const T* __restrict__ src;     // f~^n, 9 planes
+  T* __restrict__ dst;           // f~^{n+1}, 9 planes
+  const T* __restrict__ ph_src;  // phi^{n-1}
+  T* __restrict__ ph_dst;        // phi^n
+  const T* __restrict__ cf;      // compact face-stencil table [NCOMPACT]
+  const T* __restrict__ tabx;    // UX[2nx+2], VX[2nx+2]
+  const T* __restrict__ taby;    // UY[2ny+2], VY[2ny+2]
+};
+
+template <typename T>
 struct RowRegs {
   T f[9];
   T hp;
-};
-template <typename T>
-struct TfpRegs {
-  T v[9];
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// value of the lane to the right / left (the two edge lanes get their own value;
+// they are halo lanes whose results are never stored)
 template <typename T>
-struct StepBufs {
-  const T* __restrict__ src;     // f~^n, 9 planes
-  T* __restrict__ dst;           // f~^{n+1}, 9 planes
-  const T* __restrict__ ph_src;  // phi^{n-1}
-  T* __restrict__ ph_dst;        // phi^n
-  const T* __restrict__ cf;      // [2][9][NTAP] face stencils
-  const T* __restrict__ tabx;    // UX[2nx+2], VX[2nx+2]
-  const T* __restrict__ taby;    // UY[2ny+2], VY[2ny+2]
-};
+__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, LANES); }
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, LANES); }
 
 template <typename T, int R>
 struct Marcher {
@@ -76,67 +79,64 @@ struct Marcher {
   const T* __restrict__ cf;
   const T* __restrict__ tabx;
   const T* __restrict__ taby;
-  T (*bfp)[9][LROW];   // [RB][9][LROW]
-  T (*phl)[LROW];      // [4][LROW]
-  T (*svl)[2][LROW];   // [3][2][LROW]
-  T (*fel)[LROW];      // [6][LROW]
+  T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
   bool owned;
   int y0, y1, base;
   T UXc, VXc, UXe, VXe;
   T gN, gP, gH, jscale;
+  // own-column pipeline (registers)
+  T ph0, ph1, ph2, ph3;     // phi of rows r-2 .. r+1
+  T D0, D1, D2;             // phi(x+1) - phi(x-1) of rows r-1 .. r+1
+  T A0, A1, A2;             // phi(x-1) + 4 phi(x) + phi(x+1) of rows r-1 .. r+1
+  T sx0, sy0, sx1, sy1, sx2, sy2;  // s = theta n + J/RT of rows r-2 .. r
+  T fS[9];                  // dt*alpha*fbar of the face below (north face of k-1)
+  T PS, QSx, QSy;           // its collision part, see face_stage
 
   __device__ __forceinline__ int slotB(int row) const { return (row - base) % RB; }
-  __device__ __forceinline__ int slot4(int row) const { return (row - base) & 3; }
-  __device__ __forceinline__ int slot3(int row) const { return (row - base) % 3; }
 
   __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
-    int rr = wrapi(row, a.ny);
+    const int rr = wrapi(row, a.ny);
     const T* p = src + (int64_t)rr * a.pitch + col;
 #pragma unroll
     for (int i = 0; i < 9; i++) d.f[i] = p[(int64_t)i * a.plane];
     d.hp = ph_src[(int64_t)rr * a.pitch + col];
   }
 
-  // phi = sum_i f~_i (Eq. 30), same summation order as a plain loop over i
-  __device__ __forceinline__ void phi_stage(const RowRegs<T>& d, int row) const {
-    T s = d.f[0];
+  // phi = sum_i f~_i (Eq. 30) of a new row and its horizontal differences
+  __device__ __forceinline__ void phi_push(const RowRegs<T>& d) {
+    T p = d.f[0];
 #pragma unroll
-    for (int i = 1; i < 9; i++) s += d.f[i];
-    phl[slot4(row)][LPAD + lane] = s;
+    for (int i = 1; i < 9; i++) p += d.f[i];
+    const T pE = from_right(p), pW = from_left(p);
+    ph0 = ph1; ph1 = ph2; ph2 = ph3; ph3 = p;
+    D0 = D1; D1 = D2; D2 = pE - pW;
+    A0 = A1; A1 = A2; A2 = fma(T(4), p, pW + pE);
   }
 
-  // cell-centred terms of row r: normal, theta, d(phi u)/dt, S, feq -> fbar+
-  // into the LDS ring and f~+ into registers
-  __device__ __forceinline__ void cell_stage(const RowRegs<T>& d, int r,
-                                             TfpRegs<T>& tp) const {
+  // cell-centred terms of row r: isotropic normal, theta (Eqs. 2, 4),
+  // d(phi u)/dt, feq and S (Eq. 14) collapsed into fbar+ (Eq. 23) -> LDS ring
+  __device__ __forceinline__ void cell_stage(const RowRegs<T>& d, int r) {
     const int L = LPAD + lane;
-    const T* pm = phl[slot4(r - 1)];
-    const T* p0 = phl[slot4(r)];
-    const T* pp = phl[slot4(r + 1)];
-    const T pC = p0[L];
-    const T pE = p0[L + 1], pW = p0[L - 1], pN = pp[L], pS = pm[L];
-    const T pNE = pp[L + 1], pNW = pp[L - 1], pSE = pm[L + 1], pSW = pm[L - 1];
-    // isotropic gradient: (1/RT) sum_k w_k e_k phi_k
-    const T third = T(1) / T(3), twelfth = T(1) / T(12);
-    T gx = (pE - pW) * third + ((pNE - pNW) + (pSE - pSW)) * twelfth;
-    T gy = (pN - pS) * third + ((pNE - pSE) + (pNW - pSW)) * twelfth;
-    T gm = sqrt(gx * gx + gy * gy);
-    T den = gm > T(1e-12) ? gm : T(1e-12);
-    T th = a.kth * pC * (T(1) - pC) / den;     // theta / |grad phi|
-    int rr = wrapi(r, a.ny);
-    T UYr = taby[2 * rr + 1];
-    T VYr = taby[(2 * a.ny + 2) + 2 * rr + 1];
-    T Uc = UXc * UYr, Vc = VXc * VYr;          // spatial part of u at the cell
-    T dj = (gN * pC - gP * d.hp) * jscale;     // d(phi g)/dt
-    T sx = th * gx + T(3) * (Uc * dj);         // s = theta n + J / RT
-    T sy = th * gy + T(3) * (Vc * dj);
-    svl[slot3(r)][0][L] = sx;
-    svl[slot3(r)][1][L] = sy;
+    const T twelfth = T(1) / T(12);
+    // (1/RT) sum_k w_k e_k phi_k, column-summed
+    const T gx = fma(T(4), D1, D0 + D2) * twelfth;
+    const T gy = (A2 - A0) * twelfth;
+    const T pC = ph2;
+    const T gm = sqrt(fma(gx, gx, gy * gy));
+    const T den = gm > T(1e-12) ? gm : T(1e-12);
+    const T th = a.kth * pC * (T(1) - pC) / den;   // theta / |grad phi|
+    const int rr = wrapi(r, a.ny);
+    const T UYr = taby[2 * rr + 1];
+    const T VYr = taby[(2 * a.ny + 2) + 2 * rr + 1];
+    const T Uc = UXc * UYr, Vc = VXc * VYr;        // spatial part of u
+    const T dj = fma(gN, pC, -(gP * d.hp)) * jscale;   // d(phi g)/dt
+    const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
+    const T sy = fma(th, gy, T(3) * (Vc * dj));
+    sx0 = sx1; sy0 = sy1; sx1 = sx2; sy1 = sy2; sx2 = sx; sy2 = sy;
     // feq + tau S = w_i (phi + e_i . m),  m = phi u / RT + tau s
-    T uc = gN * Uc, vc = gN * Vc;
-    T mx = T(3) * pC * uc + a.tau * sx;
-    T my = T(3) * pC * vc + a.tau * sy;
+    const T mx = fma(a.tau, sx, T(3) * pC * (gN * Uc));
+    const T my = fma(a.tau, sy, T(3) * pC * (gN * Vc));
     T* bf = &bfp[slotB(r)][0][0];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
@@ -145,166 +145,153 @@ struct Marcher {
       if (ex(i) < 0) em -= mx;
       if (ey(i) > 0) em += my;
       if (ey(i) < 0) em -= my;
-      T X = T(wq(i)) * em;
-      bf[i * LROW + L] = a.cA2 * d.f[i] + a.cB2 * X;
-      tp.v[i] = a.cA * d.f[i] + a.cB * X;
+      bf[i * LROW + L] = fma(a.cA2, d.f[i], a.cB2 * (T(wq(i)) * em));
     }
   }
 
-  // reconstruction of one face value from the fbar+ ring
+  // one face value: fixed stencil over the fbar+ ring (Eqs. 24-26); the
+  // coefficients come from the compact symmetric table (uniform, scalar
+  // registers), the tap pattern is compile-time
   template <int O>
   __device__ __forceinline__ T recon(int i, int k) const {
     const int L = LPAD + lane;
-    const T* c = cf + (O * 9 + i) * NTAP;
     T v = T(0);
 #pragma unroll
     for (int t = 0; t < NTAP; t++) {
       if (tap_used(R, O, i, t)) {
         const T f = bfp[slotB(k + tap_dy(O, t))][i][L + tap_dx(O, t)];
-        v = fma(c[t], f, v);
+        v = fma(cf[compact_index(O, i, t)], f, v);
       }
     }
     return v;
   }
 
-  // faces of row k and the update of its cells
-  __device__ __forceinline__ void face_stage(int k, const TfpRegs<T>& tp, T (&fS)[9],
-                                             bool do_update) const {
+  // Faces of row k and the update of its cells.  With phi_b = sum_i fbar_i,
+  // Eq. (27) gives dt f_b,i = dt*alpha*fbar_i + dt w_i (P + e_i . Q),
+  // P = beta phi_b, Q = 3 P u_b + gamma S_b/w-part, so the flux differences
+  // split into a per-velocity part, accumulated as each fbar_i is formed, and
+  // a collision part in the 3 numbers (P, Qx, Qy) of each face.
+  __device__ __forceinline__ void face_stage(int k) {
     const int L = LPAD + lane;
-    T bN[9], bE[9];
+    const bool upd = k >= y0;
+    const int kk = wrapi(k, a.ny);
+    T out[9];
     T phN = T(0), phE = T(0);
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-      bN[i] = recon<1>(i, k);
-      phN += bN[i];
-      if (do_update) {
-        bE[i] = recon<0>(i, k);
-        phE += bE[i];
+      out[i] = T(0);
+      const T bN = recon<1>(i, k);
+      phN += bN;
+      if (ey(i) != 0) {
+        const T pn = a.dalpha * bN;
+        const T d = pn - fS[i];
+        if (upd) out[i] = ey(i) > 0 ? -d : d;
+        fS[i] = pn;
       }
+      if (upd) {
+        const T bE = recon<0>(i, k);
+        phE += bE;
+        if (ex(i) != 0) {
+          const T pe = a.dalpha * bE;
+          const T d = pe - from_left(pe);
+          out[i] = ex(i) > 0 ? out[i] - d : out[i] + d;
+        }
+      }
+      // keep one velocity's taps live at a time; other wavefronts hide the
+      // LDS latency
+      __builtin_amdgcn_sched_barrier(0);
     }
-    const int kk = wrapi(k, a.ny);
     const T* UY = taby;
     const T* VY = taby + (2 * a.ny + 2);
-    // north face (x + 1/2, y + 1): S_b = mean of the two cells (own column)
-    {
-      T sx = T(0.5) * (svl[slot3(k)][0][L] + svl[slot3(k + 1)][0][L]);
-      T sy = T(0.5) * (svl[slot3(k)][1][L] + svl[slot3(k + 1)][1][L]);
-      T ub = gH * (UXc * UY[2 * kk + 2]);
-      T vb = gH * (VXc * VY[2 * kk + 2]);
-      T P = a.beta * phN;
-      T Qx = T(3) * P * ub + a.gamma * sx;
-      T Qy = T(3) * P * vb + a.gamma * sy;
+    // north face (x + 1/2, y + 1): S_b = mean of the two cells
+    const T ubN = gH * (UXc * UY[2 * kk + 2]);
+    const T vbN = gH * (VXc * VY[2 * kk + 2]);
+    const T PN = a.beta * phN;
+    const T QNx = fma(T(3) * PN, ubN, a.gamma * (T(0.5) * (sx0 + sx1)));
+    const T QNy = fma(T(3) * PN, vbN, a.gamma * (T(0.5) * (sy0 + sy1)));
+    const T dP = PN - PS, dQx = QNx - QSx, dQy = QNy - QSy;
+    PS = PN; QSx = QNx; QSy = QNy;
+    if (!upd) return;
 #pragma unroll
-      for (int i = 0; i < 9; i++) {
-        if (ey(i) == 0) continue;
-        T em = P;
-        if (ex(i) > 0) em += Qx;
-        if (ex(i) < 0) em -= Qx;
-        if (ey(i) > 0) em += Qy;
-        if (ey(i) < 0) em -= Qy;
-        T fN = a.dalpha * bN[i] + (a.dt * T(wq(i))) * em;
-        if (do_update) {
-          T d = fN - fS[i];
-          bN[i] = ey(i) > 0 ? d : -d;   // e_iy (fN - fS), reuse bN
-        }
-        fS[i] = fN;
-      }
+    for (int i = 0; i < 9; i++) {
+      if (ey(i) == 0) continue;
+      T em = dP;
+      if (ex(i) > 0) em += dQx;
+      if (ex(i) < 0) em -= dQx;
+      em = ey(i) > 0 ? em + dQy : em - dQy;
+      const T v = (a.dt * T(wq(i))) * em;
+      out[i] = ey(i) > 0 ? out[i] - v : out[i] + v;
     }
-    if (!do_update) return;
     // east face (x + 1, y + 1/2): S_b = mean of own and east cell
-    T fE[9];
-    {
-      T sx = T(0.5) * (svl[slot3(k)][0][L] + svl[slot3(k)][0][L + 1]);
-      T sy = T(0.5) * (svl[slot3(k)][1][L] + svl[slot3(k)][1][L + 1]);
-      T ub = gH * (UXe * UY[2 * kk + 1]);
-      T vb = gH * (VXe * VY[2 * kk + 1]);
-      T P = a.beta * phE;
-      T Qx = T(3) * P * ub + a.gamma * sx;
-      T Qy = T(3) * P * vb + a.gamma * sy;
-      int q = 0;
+    const T ubE = gH * (UXe * UY[2 * kk + 1]);
+    const T vbE = gH * (VXe * VY[2 * kk + 1]);
+    const T PE = a.beta * phE;
+    const T QEx = fma(T(3) * PE, ubE, a.gamma * (T(0.5) * (sx0 + from_right(sx0))));
+    const T QEy = fma(T(3) * PE, vbE, a.gamma * (T(0.5) * (sy0 + from_right(sy0))));
+    const T eP = PE - from_left(PE), eQx = QEx - from_left(QEx), eQy = QEy - from_left(QEy);
 #pragma unroll
-      for (int i = 0; i < 9; i++) {
-        if (ex(i) == 0) continue;
-        T em = P;
-        if (ex(i) > 0) em += Qx;
-        if (ex(i) < 0) em -= Qx;
-        if (ey(i) > 0) em += Qy;
-        if (ey(i) < 0) em -= Qy;
-        fE[i] = a.dalpha * bE[i] + (a.dt * T(wq(i))) * em;
-        fel[q][L] = fE[i];
-        q++;
-      }
+    for (int i = 0; i < 9; i++) {
+      if (ex(i) == 0) continue;
+      T em = ex(i) > 0 ? eP + eQx : eP - eQx;
+      if (ey(i) > 0) em += eQy;
+      if (ey(i) < 0) em -= eQy;
+      const T v = (a.dt * T(wq(i))) * em;
+      out[i] = ex(i) > 0 ? out[i] - v : out[i] + v;
     }
-    __syncthreads();
-    // west face of this cell = east face of the lane to the left; update
-    T out[9];
-    {
-      int q = 0;
-#pragma unroll
-      for (int i = 0; i < 9; i++) {
-        T flux = T(0);
-        if (ex(i) != 0) {
-          T d = fE[i] - fel[q][L - 1];
-          flux = ex(i) > 0 ? d : -d;
-          q++;
-        }
-        if (ey(i) != 0) flux += bN[i];
-        out[i] = tp.v[i] - flux;
-      }
-    }
+    // f~+ = (4 fbar+ - f~) / 3, then f~^{n+1} = f~+ + dt L (Eqs. 9, 23, 21);
+    // f~ of row k is read again here (cache hit) rather than held in registers
+    // across the two rows of the pipeline
+    const T four3 = T(4) / T(3), third = T(1) / T(3);
     if (owned) {
       const int64_t o = (int64_t)kk * a.pitch + col;
 #pragma unroll
-      for (int i = 0; i < 9; i++) dst[(int64_t)i * a.plane + o] = out[i];
-      ph_dst[o] = phl[slot4(k)][L];
+      for (int i = 0; i < 9; i++) {
+        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * src[(int64_t)i * a.plane + o]));
+        dst[(int64_t)i * a.plane + o] = tfp + out[i];
+      }
+      ph_dst[o] = ph0;
     }
   }
 
-  // one row of the march: load r+2, phi of r+1, cell terms of r, faces of r-2
-  __device__ __forceinline__ void body(int r, RowRegs<T>& B, RowRegs<T>& C,
-                                       RowRegs<T>& D, TfpRegs<T>& Pr,
-                                       TfpRegs<T>& Pk, T (&fS)[9]) const {
+  // row r of the march: phi of r+1, cell terms of r, load r+2, faces of r-2
+  __device__ __forceinline__ void body(int r, RowRegs<T>& cur, RowRegs<T>& nxt) {
     if (r > y1 + 1) return;
-    if (r + 2 <= y1 + 2) load_row(D, r + 2);
-    phi_stage(C, r + 1);
-    __syncthreads();
-    cell_stage(B, r, Pr);
+    phi_push(nxt);
+    cell_stage(cur, r);
+    if (r + 2 <= y1 + 2) load_row(cur, r + 2);
     __syncthreads();
     const int k = r - 2;
-    if (k >= y0 - 1) face_stage(k, Pk, fS, k >= y0);
+    if (k >= y0 - 1) face_stage(k);
+    __syncthreads();
   }
 
   __device__ void run() {
-    RowRegs<T> B, C, D;
-    TfpRegs<T> P0, P1, P2;
-    T fS[9];
+    RowRegs<T> B, C;
+    ph0 = ph1 = ph2 = ph3 = T(0);
+    D0 = D1 = D2 = A0 = A1 = A2 = T(0);
+    sx0 = sy0 = sx1 = sy1 = sx2 = sy2 = T(0);
+    PS = QSx = QSy = T(0);
 #pragma unroll
     for (int i = 0; i < 9; i++) fS[i] = T(0);
     load_row(C, y0 - 3);
-    phi_stage(C, y0 - 3);
+    phi_push(C);
     load_row(B, y0 - 2);
-    phi_stage(B, y0 - 2);
+    phi_push(B);
     load_row(C, y0 - 1);
-    // r = y0-2 + 3j + {0,1,2}; tf~+ of row r sits in P[(r - y0 + 2) % 3] and
-    // that of row r-2 in P[(r - y0 + 3) % 3]
-    for (int r = y0 - 2; r <= y1 + 1; r += 3) {
-      body(r, B, C, D, P0, P1, fS);
-      body(r + 1, C, D, B, P1, P2, fS);
-      body(r + 2, D, B, C, P2, P0, fS);
+    for (int r = y0 - 2; r <= y1 + 1; r += 2) {
+      body(r, B, C);
+      body(r + 1, C, B);
     }
   }
 };
 
 template <typename T, int R>
-__global__ __launch_bounds__(LANES) void step_kernel(
+__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
     StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ ph_src, T* __restrict__ ph_dst, const T* __restrict__ cf,
     const T* __restrict__ tabx, const T* __restrict__ taby) {
   constexpr int RB = Marcher<T, R>::RB;
   __shared__ T s_bfp[RB][9][LROW];
-  __shared__ T s_phi[4][LROW];
-  __shared__ T s_sv[3][2][LROW];
-  __shared__ T s_fe[6][LROW];
 
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
   // each XCD a contiguous band of tiles (shared halos stay in one L2)
@@ -315,17 +302,14 @@ __global__ __launch_bounds__(LANES) void step_kernel(
   const int seg = logical / a.nstrips;
 
   const int lane = threadIdx.x;
-  // zero the LDS pads once (never read by owned results, kept finite)
+  // the LDS pads are never read into owned results; keep them finite
   for (int j = lane; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
-  for (int j = lane; j < 4 * LROW; j += LANES) (&s_phi[0][0])[j] = T(0);
-  for (int j = lane; j < 3 * 2 * LROW; j += LANES) (&s_sv[0][0][0])[j] = T(0);
-  for (int j = lane; j < 6 * LROW; j += LANES) (&s_fe[0][0])[j] = T(0);
   __syncthreads();
 
-  Marcher<T, R> m{a, src, dst, ph_src, ph_dst, cf, tabx, taby, s_bfp, s_phi, s_sv, s_fe};
+  Marcher<T, R> m{a, src, dst, ph_src, ph_dst, cf, tabx, taby, s_bfp};
   const int x0 = strip * OWN;
   m.lane = lane;
-  int c0 = (x0 - HALO + lane) % a.nx;
+  const int c0 = (x0 - HALO + lane) % a.nx;
   m.col = c0 < 0 ? c0 + a.nx : c0;
   const int nown = min(OWN, a.nx - x0);
   m.owned = lane >= HALO && lane < HALO + nown;
