@@ -223,10 +223,8 @@ StepBufs<T> step_bufs(const dugks_plan* P, void* state, int64_t n) {
   const Layout& L = P->L;
   const int b = (int)(n & 1);
   StepBufs<T> q;
-  q.src = at<T>(state, L.off_tf[b]);
-  q.dst = at<T>(state, L.off_tf[b ^ 1]);
-  q.ph_src = at<T>(state, L.off_ph[b]);
-  q.ph_dst = at<T>(state, L.off_ph[b ^ 1]);
+  q.src = at<T>(state, L.off_buf[b]);
+  q.dst = at<T>(state, L.off_buf[b ^ 1]);
   q.cf = at<T>(state, L.off_coef);
   q.tabx = at<T>(state, L.off_tabx);
   q.taby = at<T>(state, L.off_taby);
@@ -237,22 +235,20 @@ template <typename T>
 StepArgs<T> step_args(const dugks_plan* P) {
   const Layout& L = P->L;
   StepArgs<T> a;
-  a.pitch = L.pitch;
-  a.plane = L.plane;
+  a.CH = L.tl.CH;
   a.nx = P->p.nx;
   a.ny = P->p.ny;
   a.seg_rows = P->seg_rows;
   a.nstrips = P->nstrips;
   a.nsegs = P->nsegs;
   a.nlogical = P->nstrips * P->nsegs;
-  a.cA = T(P->cA);
-  a.cB = T(P->cB);
   a.cA2 = T(P->cA2);
-  a.cB2 = T(P->cB2);
-  a.dalpha = T(P->dt * P->alpha);
+  a.cBw0 = T(P->cB2 * wq(0));
+  a.cBw1 = T(P->cB2 * wq(1));
+  a.cBw2 = T(P->cB2 * wq(2));
+  a.pscale = T(P->beta / P->alpha);
+  a.gdt = T(0.5 * P->dt * P->gamma);
   a.dt = T(P->dt);
-  a.beta = T(P->beta);
-  a.gamma = T(P->gamma);
   a.tau = T(P->tau);
   a.kth = isfinite(P->p.width) ? T(4.0 / P->p.width) : T(0);
   a.period = P->period;
@@ -269,8 +265,8 @@ int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
   const int per = (a.nlogical + 7) / 8;
   dim3 grid(per * 8), block(LANES);
 #define DUGKS_LAUNCH(RR)                                                                   \
-  hipLaunchKernelGGL((step_kernel<T, RR>), grid, block, 0, s, a, n, q.src, q.dst, q.ph_src, \
-                     q.ph_dst, q.cf, q.tabx, q.taby)
+  hipLaunchKernelGGL((step_kernel<T, RR>), grid, block, 0, s, a, n, q.src, q.dst, q.cf, q.tabx, \
+                     q.taby)
   switch (P->p.recon) {
     case DUGKS_CENTRAL2: DUGKS_LAUNCH(DUGKS_CENTRAL2); break;
     case DUGKS_UPWIND3: DUGKS_LAUNCH(DUGKS_UPWIND3); break;
@@ -292,8 +288,9 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   h.ny = ny;
   h.precision = P->p.precision;
   h.recon = P->p.recon;
+  // the device table carries dt * alpha (Eq. 27) times the stencil
   std::vector<T> cf(NCOMPACT), tx(P->tabx.size()), ty(P->taby.size());
-  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->compact[k]);
+  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->alpha * P->compact[k]);
   for (size_t k = 0; k < tx.size(); k++) tx[k] = T(P->tabx[k]);
   for (size_t k = 0; k < ty.size(); k++) ty[k] = T(P->taby[k]);
   hipError_t e;
@@ -309,14 +306,10 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
     return hip_status(e);
   InitArgs<T> a;
   a.phi0 = phi0;
-  a.tf = at<T>(state, L.off_tf[0]);
-  a.ph = at<T>(state, L.off_ph[0]);
+  a.buf = at<T>(state, L.off_buf[0]);
   a.tabx = at<T>(state, L.off_tabx);
   a.taby = at<T>(state, L.off_taby);
-  a.pitch = L.pitch;
-  a.plane = L.plane;
-  a.nx = nx;
-  a.ny = ny;
+  a.tl = L.tl;
   a.dt = P->dt;
   a.kth = isfinite(P->p.width) ? 4.0 / P->p.width : 0.0;
   dim3 grid((nx + 255) / 256, ny), block(256);
@@ -325,8 +318,8 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   // M0: FP64 total of phi0 itself (not of its rounded f~)
   double* part = at<double>(state, L.off_scratch);
   StateHeader* hd = at<StateHeader>(state, 0);
-  hipLaunchKernelGGL((mass_partial_kernel<double, 1>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
-                     phi0, (int64_t)nx, (int64_t)0, nx, ny, part);
+  hipLaunchKernelGGL((mass_partial_kernel<double, false>), dim3(MASS_BLOCKS), dim3(MASS_THREADS),
+                     0, s, phi0, L.tl, part);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass0,
                      &hd->mass_now);
   if ((e = hipGetLastError())) return hip_status(e);
@@ -339,8 +332,8 @@ int do_phi(const dugks_plan* P, const void* state, int64_t n, void* out, hipStre
   const Layout& L = P->L;
   const int nx = P->p.nx, ny = P->p.ny;
   dim3 grid((nx + 255) / 256, ny), block(256);
-  hipLaunchKernelGGL((phi_kernel<T>), grid, block, 0, s, at<T>(state, L.off_tf[n & 1]),
-                     L.pitch, L.plane, nx, ny, static_cast<T*>(out));
+  hipLaunchKernelGGL((phi_kernel<T>), grid, block, 0, s, at<T>(state, L.off_buf[n & 1]), L.tl,
+                     static_cast<T*>(out));
   return hip_status(hipGetLastError());
 }
 
@@ -349,8 +342,8 @@ int do_export(const dugks_plan* P, const void* state, int64_t n, void* out, hipS
   const Layout& L = P->L;
   const int nx = P->p.nx, ny = P->p.ny;
   dim3 grid((nx + 255) / 256, ny, 9), block(256);
-  hipLaunchKernelGGL((export_kernel<T>), grid, block, 0, s, at<T>(state, L.off_tf[n & 1]),
-                     L.pitch, L.plane, nx, ny, static_cast<T*>(out));
+  hipLaunchKernelGGL((export_kernel<T>), grid, block, 0, s, at<T>(state, L.off_buf[n & 1]), L.tl,
+                     static_cast<T*>(out));
   return hip_status(hipGetLastError());
 }
 
@@ -359,8 +352,8 @@ int do_mass(const dugks_plan* P, void* state, int64_t n, double* out, hipStream_
   const Layout& L = P->L;
   double* part = at<double>(state, L.off_scratch);
   StateHeader* hd = at<StateHeader>(state, 0);
-  hipLaunchKernelGGL((mass_partial_kernel<T, 9>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
-                     at<T>(state, L.off_tf[n & 1]), L.pitch, L.plane, P->p.nx, P->p.ny, part);
+  hipLaunchKernelGGL((mass_partial_kernel<T, true>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
+                     at<T>(state, L.off_buf[n & 1]), L.tl, part);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass_now, out);
   return hip_status(hipGetLastError());
 }
@@ -375,7 +368,7 @@ int do_correct(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
     int rc = do_mass<T>(P, state, n, nullptr, s);
     if (rc) return rc;
     hipLaunchKernelGGL((mass_correct_kernel<T>), grid, block, 0, s,
-                       at<T>(state, L.off_tf[n & 1]), L.pitch, L.plane, nx, ny, hd);
+                       at<T>(state, L.off_buf[n & 1]), L.tl, hd);
     if (hipGetLastError() != hipSuccess) return DUGKS_EDEVICE;
   }
   return DUGKS_OK;

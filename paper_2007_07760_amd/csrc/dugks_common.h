@@ -98,7 +98,24 @@ constexpr int LPAD = 2;                 // LDS row padding each side
 constexpr int LROW = LANES + 2 * LPAD;  // LDS row length (elements)
 
 // ------------------------------------------------------------- state layout
-// [header 256 B][coef table][x tables][y tables][tf A][tf B][phi A][phi B][scratch]
+// The distributions live in strip chunks: the grid is cut into strips of OWN
+// columns (the columns one wavefront owns), and row y of strip s holds the 9
+// planes of f~ and the phi history plane (plane 9) of its OWN columns in one
+// contiguous chunk, padded to whole 128-byte lines:
+//     element (i, y, x) at ((x / OWN) * ny + y) * CH + i * OWN + x % OWN.
+// A wavefront's row then reads one contiguous chunk (plus 3-column halo
+// slivers of the neighbour strips) and writes whole cache lines.
+constexpr int NPLANE = 10;          // 9 distributions + phi history
+struct Tiling {
+  int nx, ny, nstrips;
+  int64_t CH;                       // chunk length (elements)
+  __host__ __device__ int64_t idx(int i, int y, int x) const {
+    const int s = x / OWN;
+    return ((int64_t)s * ny + y) * CH + (int64_t)i * OWN + (x - s * OWN);
+  }
+};
+
+// [header 256 B][coef table][x tables][y tables][buffer A][buffer B][scratch]
 struct StateHeader {
   uint64_t magic;
   double mass0;        // FP64 total of phi0
@@ -115,9 +132,8 @@ constexpr int MASS_THREADS = 256;
 
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)
-  int64_t pitch;       // elements per row
-  int64_t plane;       // elements per plane (padded)
-  size_t off_coef, off_tabx, off_taby, off_tf[2], off_ph[2], off_scratch, total;
+  Tiling tl;
+  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, total;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -125,11 +141,12 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline Layout make_layout(int nx, int ny, int precision) {
   Layout L;
   L.esize = precision == DUGKS_F64 ? 8 : 4;
-  int64_t row_align = 256 / (int64_t)L.esize;
-  L.pitch = (int64_t)align_up((size_t)nx, (size_t)row_align);
-  // planes padded by one extra 2 KB stretch so the 9 planes do not alias in
-  // the HBM channel hash at power-of-two sizes
-  L.plane = L.pitch * ny + 2048 / (int64_t)L.esize;
+  const int64_t line = 128 / (int64_t)L.esize;
+  L.tl.nx = nx;
+  L.tl.ny = ny;
+  L.tl.nstrips = (nx + OWN - 1) / OWN;
+  L.tl.CH = (NPLANE * OWN + line - 1) / line * line;
+  const size_t buf_elems = (size_t)L.tl.nstrips * ny * L.tl.CH;
   size_t off = sizeof(StateHeader);
   L.off_coef = off;
   off = align_up(off + NCOMPACT * L.esize, 256);
@@ -138,12 +155,8 @@ inline Layout make_layout(int nx, int ny, int precision) {
   L.off_taby = off;
   off = align_up(off + 2 * (2 * (size_t)ny + 2) * L.esize, 256);
   for (int b = 0; b < 2; b++) {
-    L.off_tf[b] = off;
-    off = align_up(off + 9 * (size_t)L.plane * L.esize, 256);
-  }
-  for (int b = 0; b < 2; b++) {
-    L.off_ph[b] = off;
-    off = align_up(off + (size_t)L.plane * L.esize, 256);
+    L.off_buf[b] = off;
+    off = align_up(off + buf_elems * L.esize, 256);
   }
   L.off_scratch = off;
   off = align_up(off + 2 * MASS_BLOCKS * sizeof(double) + 64, 256);

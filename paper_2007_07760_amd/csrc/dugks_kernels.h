@@ -27,13 +27,14 @@ namespace dugks {
 // lets the uniform coefficient and table reads use the scalar cache.
 template <typename T>
 struct StepArgs {
-  int64_t pitch, plane;
+  int64_t CH;            // strip-chunk length (elements), see Tiling
   int nx, ny;
   int seg_rows, nstrips, nsegs, nlogical;
-  T cA, cB;       // f~+   = cA f~ + cB (feq + tau S)
-  T cA2, cB2;     // fbar+ = cA2 f~ + cB2 (feq + tau S)
-  T dalpha;       // dt * 2tau/(2tau+h)
-  T dt, beta, gamma, tau, kth;   // kth = 4/W (0: theta off)
+  T cA2;                 // fbar+ = cA2 f~ + cB2 (feq + tau S)
+  T cBw0, cBw1, cBw2;    // cB2 * w for the rest, axis and diagonal weights
+  T pscale;              // beta / alpha (the stencil table carries dt*alpha)
+  T gdt;                 // dt * gamma / 2 (face S is the mean of two cells)
+  T dt, tau, kth;        // kth = 4/W (0: theta off)
   double period;  // time modulation cos(pi t / period); 0 = steady
   double dtd, hd; // dt, h in FP64 for the time factors
   int jzero;      // 1: d(phi u)/dt = 0 on every step
@@ -41,10 +42,8 @@ struct StepArgs {
 
 template <typename T>
 struct StepBufs {
-  const T* __restrict__ src;     // f~^n, 9 planes
-  T* __restrict__ dst;           // f~^{n+1}, 9 planes
-  const T* __restrict__ ph_src;  // phi^{n-1}
-  T* __restrict__ ph_dst;        // phi^n
+  const T* __restrict__ src;     // f~^n and phi^{n-1} (strip chunks)
+  T* __restrict__ dst;           // f~^{n+1} and phi^n
   const T* __restrict__ cf;      // compact face-stencil table [NCOMPACT]
   const T* __restrict__ tabx;    // UX[2nx+2], VX[2nx+2]
   const T* __restrict__ taby;    // UY[2ny+2], VY[2ny+2]
@@ -60,12 +59,36 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-// value of the lane to the right / left (the two edge lanes get their own value;
-// they are halo lanes whose results are never stored)
+// Value of the lane to the right / left through the DPP wavefront shifts
+// (wave_shl:1 moves lane i+1 into lane i, wave_shr:1 lane i-1); the two edge
+// lanes keep their own value -- they are halo lanes whose results are never
+// stored.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
 template <typename T>
-__device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, LANES); }
+__device__ __forceinline__ T from_right(T v) { return dpp_shift<0x130>(v); }
 template <typename T>
-__device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, LANES); }
+__device__ __forceinline__ T from_left(T v) { return dpp_shift<0x138>(v); }
+
+// Ordering point for LDS traffic inside the (single-wavefront) workgroup: a
+// wavefront's LDS operations execute in program order, so only the compiler
+// must not move them across this point; no wait for outstanding operations.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, int R>
 struct Marcher {
@@ -74,13 +97,12 @@ struct Marcher {
   const StepArgs<T>& a;
   const T* __restrict__ src;
   T* __restrict__ dst;
-  const T* __restrict__ ph_src;
-  T* __restrict__ ph_dst;
   const T* __restrict__ cf;
   const T* __restrict__ tabx;
   const T* __restrict__ taby;
   T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
+  int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
   bool owned;
   int y0, y1, base;
   T UXc, VXc, UXe, VXe;
@@ -95,19 +117,24 @@ struct Marcher {
 
   __device__ __forceinline__ int slotB(int row) const { return (row - base) % RB; }
 
-  __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
-    const int rr = wrapi(row, a.ny);
-    const T* p = src + (int64_t)rr * a.pitch + col;
-#pragma unroll
-    for (int i = 0; i < 9; i++) d.f[i] = p[(int64_t)i * a.plane];
-    d.hp = ph_src[(int64_t)rr * a.pitch + col];
+  // element (plane i, row rr) of the lane's column: uniform row/plane part
+  // plus the lane's chunk offset
+  __device__ __forceinline__ const T* at_src(int i, int rr) const {
+    return src + ((int64_t)rr * a.CH + i * OWN) + loff;
   }
 
-  // phi = sum_i f~_i (Eq. 30) of a new row and its horizontal differences
-  __device__ __forceinline__ void phi_push(const RowRegs<T>& d) {
-    T p = d.f[0];
+  __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
+    const int rr = wrapi(row, a.ny);
 #pragma unroll
-    for (int i = 1; i < 9; i++) p += d.f[i];
+    for (int i = 0; i < 9; i++) d.f[i] = *at_src(i, rr);
+    d.hp = *at_src(9, rr);
+  }
+
+  // phi = sum_i f~_i (Eq. 30, pairwise) of a new row and its horizontal
+  // differences
+  __device__ __forceinline__ void phi_push(const RowRegs<T>& d) {
+    const T p = (((d.f[0] + d.f[1]) + (d.f[2] + d.f[3])) +
+                 ((d.f[4] + d.f[5]) + (d.f[6] + d.f[7]))) + d.f[8];
     const T pE = from_right(p), pW = from_left(p);
     ph0 = ph1; ph1 = ph2; ph2 = ph3; ph3 = p;
     D0 = D1; D1 = D2; D2 = pE - pW;
@@ -134,19 +161,23 @@ struct Marcher {
     const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
     const T sy = fma(th, gy, T(3) * (Vc * dj));
     sx0 = sx1; sy0 = sy1; sx1 = sx2; sy1 = sy2; sx2 = sx; sy2 = sy;
-    // feq + tau S = w_i (phi + e_i . m),  m = phi u / RT + tau s
+    // cB2 (feq + tau S)_i = cB2 w_i (phi + e_i . m),  m = phi u / RT + tau s,
+    // formed per weight class (rest, axis, diagonal) and per direction pair
     const T mx = fma(a.tau, sx, T(3) * pC * (gN * Uc));
     const T my = fma(a.tau, sy, T(3) * pC * (gN * Vc));
+    const T P0 = a.cBw0 * pC, P1 = a.cBw1 * pC, P2 = a.cBw2 * pC;
+    const T X1 = a.cBw1 * mx, Y1 = a.cBw1 * my;
+    const T X2 = a.cBw2 * mx, Y2 = a.cBw2 * my;
+    const T dpp = X2 + Y2, dmp = Y2 - X2;
+    T t[9];
+    t[0] = P0;
+    t[1] = P1 + X1; t[5] = P1 - X1;
+    t[3] = P1 + Y1; t[7] = P1 - Y1;
+    t[2] = P2 + dpp; t[6] = P2 - dpp;
+    t[4] = P2 + dmp; t[8] = P2 - dmp;
     T* bf = &bfp[slotB(r)][0][0];
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-      T em = pC;
-      if (ex(i) > 0) em += mx;
-      if (ex(i) < 0) em -= mx;
-      if (ey(i) > 0) em += my;
-      if (ey(i) < 0) em -= my;
-      bf[i * LROW + L] = fma(a.cA2, d.f[i], a.cB2 * (T(wq(i)) * em));
-    }
+    for (int i = 0; i < 9; i++) bf[i * LROW + L] = fma(a.cA2, d.f[i], t[i]);
   }
 
   // one face value: fixed stencil over the fbar+ ring (Eqs. 24-26); the
@@ -180,19 +211,17 @@ struct Marcher {
 #pragma unroll
     for (int i = 0; i < 9; i++) {
       out[i] = T(0);
-      const T bN = recon<1>(i, k);
-      phN += bN;
+      const T pn = recon<1>(i, k);      // dt*alpha*fbar_i (scaled stencil)
+      phN += pn;
       if (ey(i) != 0) {
-        const T pn = a.dalpha * bN;
         const T d = pn - fS[i];
         if (upd) out[i] = ey(i) > 0 ? -d : d;
         fS[i] = pn;
       }
       if (upd) {
-        const T bE = recon<0>(i, k);
-        phE += bE;
+        const T pe = recon<0>(i, k);
+        phE += pe;
         if (ex(i) != 0) {
-          const T pe = a.dalpha * bE;
           const T d = pe - from_left(pe);
           out[i] = ex(i) > 0 ? out[i] - d : out[i] + d;
         }
@@ -206,50 +235,56 @@ struct Marcher {
     // north face (x + 1/2, y + 1): S_b = mean of the two cells
     const T ubN = gH * (UXc * UY[2 * kk + 2]);
     const T vbN = gH * (VXc * VY[2 * kk + 2]);
-    const T PN = a.beta * phN;
-    const T QNx = fma(T(3) * PN, ubN, a.gamma * (T(0.5) * (sx0 + sx1)));
-    const T QNy = fma(T(3) * PN, vbN, a.gamma * (T(0.5) * (sy0 + sy1)));
+    // phN = dt*alpha*phi_b; P = beta phi_b, Q = 3 P u_b + gamma s_b, all
+    // carried pre-multiplied by dt so that dt f_b,i = pn_i + w_i (P + e_i.Q)
+    const T PN = a.pscale * phN;
+    const T QNx = fma(T(3) * PN, ubN, a.gdt * (sx0 + sx1));
+    const T QNy = fma(T(3) * PN, vbN, a.gdt * (sy0 + sy1));
     const T dP = PN - PS, dQx = QNx - QSx, dQy = QNy - QSy;
     PS = PN; QSx = QNx; QSy = QNy;
     if (!upd) return;
-#pragma unroll
-    for (int i = 0; i < 9; i++) {
-      if (ey(i) == 0) continue;
-      T em = dP;
-      if (ex(i) > 0) em += dQx;
-      if (ex(i) < 0) em -= dQx;
-      em = ey(i) > 0 ? em + dQy : em - dQy;
-      const T v = (a.dt * T(wq(i))) * em;
-      out[i] = ey(i) > 0 ? out[i] - v : out[i] + v;
+    {
+      // i = 3, 7 (axis, w = 1/9) and 2, 4, 6, 8 (diagonal, w = 1/36)
+      const T a1 = T(1.0 / 9.0) * dP, ay1 = T(1.0 / 9.0) * dQy;
+      const T a2 = T(1.0 / 36.0) * dP, ax2 = T(1.0 / 36.0) * dQx, ay2 = T(1.0 / 36.0) * dQy;
+      out[3] -= a1 + ay1;
+      out[7] += a1 - ay1;
+      out[2] -= (a2 + ax2) + ay2;
+      out[4] -= (a2 - ax2) + ay2;
+      out[6] += (a2 - ax2) - ay2;
+      out[8] += (a2 + ax2) - ay2;
     }
     // east face (x + 1, y + 1/2): S_b = mean of own and east cell
     const T ubE = gH * (UXe * UY[2 * kk + 1]);
     const T vbE = gH * (VXe * VY[2 * kk + 1]);
-    const T PE = a.beta * phE;
-    const T QEx = fma(T(3) * PE, ubE, a.gamma * (T(0.5) * (sx0 + from_right(sx0))));
-    const T QEy = fma(T(3) * PE, vbE, a.gamma * (T(0.5) * (sy0 + from_right(sy0))));
+    const T PE = a.pscale * phE;
+    const T QEx = fma(T(3) * PE, ubE, a.gdt * (sx0 + from_right(sx0)));
+    const T QEy = fma(T(3) * PE, vbE, a.gdt * (sy0 + from_right(sy0)));
     const T eP = PE - from_left(PE), eQx = QEx - from_left(QEx), eQy = QEy - from_left(QEy);
-#pragma unroll
-    for (int i = 0; i < 9; i++) {
-      if (ex(i) == 0) continue;
-      T em = ex(i) > 0 ? eP + eQx : eP - eQx;
-      if (ey(i) > 0) em += eQy;
-      if (ey(i) < 0) em -= eQy;
-      const T v = (a.dt * T(wq(i))) * em;
-      out[i] = ex(i) > 0 ? out[i] - v : out[i] + v;
+    {
+      // i = 1, 5 (axis) and 2, 4, 6, 8 (diagonal)
+      const T a1 = T(1.0 / 9.0) * eP, ax1 = T(1.0 / 9.0) * eQx;
+      const T a2 = T(1.0 / 36.0) * eP, ax2 = T(1.0 / 36.0) * eQx, ay2 = T(1.0 / 36.0) * eQy;
+      out[1] -= a1 + ax1;
+      out[5] += a1 - ax1;
+      out[2] -= (a2 + ax2) + ay2;
+      out[8] -= (a2 + ax2) - ay2;
+      out[6] += (a2 - ax2) - ay2;
+      out[4] += (a2 - ax2) + ay2;
     }
     // f~+ = (4 fbar+ - f~) / 3, then f~^{n+1} = f~+ + dt L (Eqs. 9, 23, 21);
     // f~ of row k is read again here (cache hit) rather than held in registers
     // across the two rows of the pipeline
     const T four3 = T(4) / T(3), third = T(1) / T(3);
     if (owned) {
-      const int64_t o = (int64_t)kk * a.pitch + col;
+      // the new row is not read again by this launch: stream it past the caches
+      T* o = dst + (int64_t)kk * a.CH + loff;
 #pragma unroll
       for (int i = 0; i < 9; i++) {
-        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * src[(int64_t)i * a.plane + o]));
-        dst[(int64_t)i * a.plane + o] = tfp + out[i];
+        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * *at_src(i, kk)));
+        __builtin_nontemporal_store(tfp + out[i], o + i * OWN);
       }
-      ph_dst[o] = ph0;
+      __builtin_nontemporal_store(ph0, o + 9 * OWN);
     }
   }
 
@@ -259,10 +294,10 @@ struct Marcher {
     phi_push(nxt);
     cell_stage(cur, r);
     if (r + 2 <= y1 + 2) load_row(cur, r + 2);
-    __syncthreads();
+    wave_sync();
     const int k = r - 2;
     if (k >= y0 - 1) face_stage(k);
-    __syncthreads();
+    wave_sync();
   }
 
   __device__ void run() {
@@ -288,8 +323,7 @@ struct Marcher {
 template <typename T, int R>
 __global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
     StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
-    const T* __restrict__ ph_src, T* __restrict__ ph_dst, const T* __restrict__ cf,
-    const T* __restrict__ tabx, const T* __restrict__ taby) {
+    const T* __restrict__ cf, const T* __restrict__ tabx, const T* __restrict__ taby) {
   constexpr int RB = Marcher<T, R>::RB;
   __shared__ T s_bfp[RB][9][LROW];
 
@@ -306,11 +340,15 @@ __global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
   for (int j = lane; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
   __syncthreads();
 
-  Marcher<T, R> m{a, src, dst, ph_src, ph_dst, cf, tabx, taby, s_bfp};
+  Marcher<T, R> m{a, src, dst, cf, tabx, taby, s_bfp};
   const int x0 = strip * OWN;
   m.lane = lane;
   const int c0 = (x0 - HALO + lane) % a.nx;
   m.col = c0 < 0 ? c0 + a.nx : c0;
+  {
+    const int cs = m.col / OWN;
+    m.loff = (int64_t)cs * a.ny * a.CH + (m.col - cs * OWN);
+  }
   const int nown = min(OWN, a.nx - x0);
   m.owned = lane >= HALO && lane < HALO + nown;
   m.y0 = seg * a.seg_rows;
@@ -340,12 +378,10 @@ __global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
 template <typename T>
 struct InitArgs {
   const double* __restrict__ phi0;  // [ny][nx] dense
-  T* __restrict__ tf;               // 9 planes
-  T* __restrict__ ph;               // phi history plane
+  T* __restrict__ buf;              // strip chunks: f~^0 and phi history
   const T* __restrict__ tabx;
   const T* __restrict__ taby;
-  int64_t pitch, plane;
-  int nx, ny;
+  Tiling tl;
   double dt, kth;
 };
 
@@ -354,9 +390,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= a.nx || y >= a.ny) return;
+  const int nx = a.tl.nx, ny = a.tl.ny;
+  if (x >= nx || y >= ny) return;
   auto P = [&](int dx, int dy) {
-    return a.phi0[(int64_t)wrapi(y + dy, a.ny) * a.nx + wrapi(x + dx, a.nx)];
+    return a.phi0[(int64_t)wrapi(y + dy, ny) * nx + wrapi(x + dx, nx)];
   };
   const double pC = P(0, 0);
   const double gx = (P(1, 0) - P(-1, 0)) / 3.0 +
@@ -368,45 +405,41 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
   const double th = a.kth * pC * (1.0 - pC);
   const double nvx = gx / den, nvy = gy / den;
   const double u = (double)a.tabx[2 * x + 1] * (double)a.taby[2 * y + 1];
-  const double v = (double)a.tabx[(2 * a.nx + 2) + 2 * x + 1] *
-                   (double)a.taby[(2 * a.ny + 2) + 2 * y + 1];
-  const int64_t o = (int64_t)y * a.pitch + x;
+  const double v = (double)a.tabx[(2 * nx + 2) + 2 * x + 1] *
+                   (double)a.taby[(2 * ny + 2) + 2 * y + 1];
 #pragma unroll
   for (int i = 0; i < 9; i++) {
     const double eu = ex(i) * u + ey(i) * v;
     const double en = ex(i) * nvx + ey(i) * nvy;
     const double feq = wq(i) * pC * (1.0 + 3.0 * eu);
     const double src = wq(i) * th * en;
-    a.tf[(int64_t)i * a.plane + o] = T(feq - 0.5 * a.dt * src);
+    a.buf[a.tl.idx(i, y, x)] = T(feq - 0.5 * a.dt * src);
   }
-  a.ph[o] = T(pC);
+  a.buf[a.tl.idx(9, y, x)] = T(pC);
 }
 
 // ------------------------------------------------------------------ phi
 template <typename T>
-__global__ __launch_bounds__(256) void phi_kernel(const T* __restrict__ tf,
-                                                  int64_t pitch, int64_t plane,
-                                                  int nx, int ny,
+__global__ __launch_bounds__(256) void phi_kernel(const T* __restrict__ buf, Tiling tl,
                                                   T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= nx || y >= ny) return;
-  const int64_t o = (int64_t)y * pitch + x;
-  T s = tf[o];
+  if (x >= tl.nx || y >= tl.ny) return;
+  const int64_t o = tl.idx(0, y, x);
+  T s = buf[o];
 #pragma unroll
-  for (int i = 1; i < 9; i++) s += tf[(int64_t)i * plane + o];
-  out[(int64_t)y * nx + x] = s;
+  for (int i = 1; i < 9; i++) s += buf[o + i * OWN];
+  out[(int64_t)y * tl.nx + x] = s;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void export_kernel(const T* __restrict__ tf, int64_t pitch,
-                                                     int64_t plane, int nx, int ny,
+__global__ __launch_bounds__(256) void export_kernel(const T* __restrict__ buf, Tiling tl,
                                                      T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   const int i = blockIdx.z;
-  if (x >= nx || y >= ny) return;
-  out[((int64_t)i * ny + y) * nx + x] = tf[(int64_t)i * plane + (int64_t)y * pitch + x];
+  if (x >= tl.nx || y >= tl.ny) return;
+  out[((int64_t)i * tl.ny + y) * tl.nx + x] = buf[tl.idx(i, y, x)];
 }
 
 // ------------------------------------------------------------------ mass
@@ -422,21 +455,27 @@ __device__ __forceinline__ void neu_add(double& s, double& c, double v) {
 
 // block partials of sum(phi) over a fixed cell partition: partial b covers the
 // cells b, b + MASS_BLOCKS*MASS_THREADS, ... of thread order; every reduction
-// order is fixed, so the result is bitwise reproducible.
-template <typename T, int NPL>
+// order is fixed, so the result is bitwise reproducible.  STATE: phi = sum of
+// the 9 distributions in strip chunks; otherwise a dense [ny][nx] FP64 field.
+template <typename T, bool STATE>
 __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
-    const T* __restrict__ tf, int64_t pitch, int64_t plane, int nx, int ny,
-    double* __restrict__ part) {
+    const T* __restrict__ f, Tiling tl, double* __restrict__ part) {
   __shared__ double ss[MASS_THREADS], sc[MASS_THREADS];
-  const int64_t N = (int64_t)nx * ny;
+  const int nx = tl.nx;
+  const int64_t N = (int64_t)nx * tl.ny;
   double s = 0.0, c = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * MASS_THREADS + threadIdx.x; j < N;
        j += (int64_t)MASS_BLOCKS * MASS_THREADS) {
     const int y = (int)(j / nx), x = (int)(j % nx);
-    const int64_t o = (int64_t)y * pitch + x;
-    double v = (double)tf[o];
+    double v;
+    if (STATE) {
+      const int64_t o = tl.idx(0, y, x);
+      v = (double)f[o];
 #pragma unroll
-    for (int i = 1; i < NPL; i++) v += (double)tf[(int64_t)i * plane + o];
+      for (int i = 1; i < 9; i++) v += (double)f[o + i * OWN];
+    } else {
+      v = (double)f[j];
+    }
     neu_add(s, c, v);
   }
   ss[threadIdx.x] = s;
@@ -474,16 +513,15 @@ __global__ __launch_bounds__(64) void mass_final_kernel(const double* __restrict
 // f~_i += w_i (M0 - M) / (nx ny)
 template <typename T>
 __global__ __launch_bounds__(256) void mass_correct_kernel(
-    T* __restrict__ tf, int64_t pitch, int64_t plane, int nx, int ny,
-    const StateHeader* __restrict__ hdr) {
+    T* __restrict__ buf, Tiling tl, const StateHeader* __restrict__ hdr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= nx || y >= ny) return;
-  const double delta = (hdr->mass0 - hdr->mass_now) / ((double)nx * (double)ny);
-  const int64_t o = (int64_t)y * pitch + x;
+  if (x >= tl.nx || y >= tl.ny) return;
+  const double delta = (hdr->mass0 - hdr->mass_now) / ((double)tl.nx * (double)tl.ny);
+  const int64_t o = tl.idx(0, y, x);
 #pragma unroll
   for (int i = 0; i < 9; i++) {
-    T& f = tf[(int64_t)i * plane + o];
+    T& f = buf[o + i * OWN];
     f = T((double)f + wq(i) * delta);
   }
 }
