@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -206,6 +207,30 @@ int validate(const dugks_params* p) {
 
 bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
+// Default rows per wavefront.  Resident wavefronts of the step kernel on one
+// MI355X (256 CUs; per CU 8 in FP64 and 16 in FP32, limited by the LDS ring and
+// registers, 6/12 for the 5-row ring of central-4).  A wavefront marches
+// seg + 4 rows of work; the launch runs in ceil(tiles / resident) rounds, so
+// pick the segment that minimises rounds * (seg + 4): whole rounds, little
+// halo.  The autotuner replaces this by measurement.
+int default_tile_rows(const dugks_params& p, int nstrips) {
+  const bool c4 = p.recon == DUGKS_CENTRAL4;
+  const int per_cu = p.precision == DUGKS_F64 ? (c4 ? 6 : 8) : (c4 ? 12 : 16);
+  const long resident = 256L * per_cu;
+  int best = 64;
+  long best_cost = -1;
+  for (int seg = 16; seg <= 256; seg += 4) {
+    const long tiles = (long)nstrips * ((p.ny + seg - 1) / seg);
+    const long rounds = (tiles + resident - 1) / resident;
+    const long cost = rounds * (long)(std::min(seg, p.ny) + 4);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = seg;
+    }
+  }
+  return best;
+}
+
 int hip_status(hipError_t e) { return e == hipSuccess ? DUGKS_OK : DUGKS_EDEVICE; }
 
 template <typename T>
@@ -407,9 +432,9 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
     return DUGKS_EINVAL;   // cannot happen for the schemes built in
   }
   make_tables(P);
-  P->seg_rows = p->tile_rows > 0 ? p->tile_rows : 64;
-  if (P->seg_rows > p->ny) P->seg_rows = p->ny;
   P->nstrips = (p->nx + OWN - 1) / OWN;
+  P->seg_rows = p->tile_rows > 0 ? p->tile_rows : default_tile_rows(*p, P->nstrips);
+  if (P->seg_rows > p->ny) P->seg_rows = p->ny;
   P->nsegs = (p->ny + P->seg_rows - 1) / P->seg_rows;
   *out = P;
   return DUGKS_OK;

@@ -117,17 +117,17 @@ struct Marcher {
 
   __device__ __forceinline__ int slotB(int row) const { return (row - base) % RB; }
 
-  // element (plane i, row rr) of the lane's column: uniform row/plane part
-  // plus the lane's chunk offset
-  __device__ __forceinline__ const T* at_src(int i, int rr) const {
-    return src + ((int64_t)rr * a.CH + i * OWN) + loff;
+  // the lane's column in row rr of the source; plane i sits i * OWN further,
+  // which the loads take as an immediate offset
+  __device__ __forceinline__ const T* row_src(int rr) const {
+    return src + (int64_t)rr * a.CH + loff;
   }
 
   __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
-    const int rr = wrapi(row, a.ny);
+    const T* p = row_src(wrapi(row, a.ny));
 #pragma unroll
-    for (int i = 0; i < 9; i++) d.f[i] = *at_src(i, rr);
-    d.hp = *at_src(9, rr);
+    for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
+    d.hp = p[9 * OWN];
   }
 
   // phi = sum_i f~_i (Eq. 30, pairwise) of a new row and its horizontal
@@ -279,9 +279,10 @@ struct Marcher {
     if (owned) {
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
+      const T* p = row_src(kk);
 #pragma unroll
       for (int i = 0; i < 9; i++) {
-        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * *at_src(i, kk)));
+        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * p[i * OWN]));
         __builtin_nontemporal_store(tfp + out[i], o + i * OWN);
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
