@@ -267,10 +267,7 @@ StepArgs<T> step_args(const dugks_plan* P) {
   a.nstrips = P->nstrips;
   a.nsegs = P->nsegs;
   a.nlogical = P->nstrips * P->nsegs;
-  a.cA2 = T(P->cA2);
-  a.cBw0 = T(P->cB2 * wq(0));
-  a.cBw1 = T(P->cB2 * wq(1));
-  a.cBw2 = T(P->cB2 * wq(2));
+  a.cB2 = T(P->cB2);
   a.pscale = T(P->beta / P->alpha);
   a.gdt = T(0.5 * P->dt * P->gamma);
   a.dt = T(P->dt);

@@ -30,8 +30,7 @@ struct StepArgs {
   int64_t CH;            // strip-chunk length (elements), see Tiling
   int nx, ny;
   int seg_rows, nstrips, nsegs, nlogical;
-  T cA2;                 // fbar+ = cA2 f~ + cB2 (feq + tau S)
-  T cBw0, cBw1, cBw2;    // cB2 * w for the rest, axis and diagonal weights
+  T cB2;                 // fbar+ = f~ + cB2 (feq + tau S - f~)
   T pscale;              // beta / alpha (the stencil table carries dt*alpha)
   T gdt;                 // dt * gamma / 2 (face S is the mean of two cells)
   T dt, tau, kth;        // kth = 4/W (0: theta off)
@@ -161,23 +160,26 @@ struct Marcher {
     const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
     const T sy = fma(th, gy, T(3) * (Vc * dj));
     sx0 = sx1; sy0 = sy1; sx1 = sx2; sy1 = sy2; sx2 = sx; sy2 = sy;
-    // cB2 (feq + tau S)_i = cB2 w_i (phi + e_i . m),  m = phi u / RT + tau s,
-    // formed per weight class (rest, axis, diagonal) and per direction pair
+    // X_i = (feq + tau S)_i = w_i (phi + e_i . m),  m = phi u / RT + tau s,
+    // per weight class and direction pair, the rest weight taking what the
+    // others leave so that sum_i X_i = phi with no systematic rounding bias
     const T mx = fma(a.tau, sx, T(3) * pC * (gN * Uc));
     const T my = fma(a.tau, sy, T(3) * pC * (gN * Vc));
-    const T P0 = a.cBw0 * pC, P1 = a.cBw1 * pC, P2 = a.cBw2 * pC;
-    const T X1 = a.cBw1 * mx, Y1 = a.cBw1 * my;
-    const T X2 = a.cBw2 * mx, Y2 = a.cBw2 * my;
+    const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+    const T P1 = w1 * pC, P2 = w2 * pC;
+    const T X1 = w1 * mx, Y1 = w1 * my;
+    const T X2 = w2 * mx, Y2 = w2 * my;
     const T dpp = X2 + Y2, dmp = Y2 - X2;
-    T t[9];
-    t[0] = P0;
-    t[1] = P1 + X1; t[5] = P1 - X1;
-    t[3] = P1 + Y1; t[7] = P1 - Y1;
-    t[2] = P2 + dpp; t[6] = P2 - dpp;
-    t[4] = P2 + dmp; t[8] = P2 - dmp;
+    T x[9];
+    x[0] = fma(T(-4), P1 + P2, pC);
+    x[1] = P1 + X1; x[5] = P1 - X1;
+    x[3] = P1 + Y1; x[7] = P1 - Y1;
+    x[2] = P2 + dpp; x[6] = P2 - dpp;
+    x[4] = P2 + dmp; x[8] = P2 - dmp;
+    // fbar+ in increment form: its moments follow those of X exactly
     T* bf = &bfp[slotB(r)][0][0];
 #pragma unroll
-    for (int i = 0; i < 9; i++) bf[i * LROW + L] = fma(a.cA2, d.f[i], t[i]);
+    for (int i = 0; i < 9; i++) bf[i * LROW + L] = fma(a.cB2, x[i] - d.f[i], d.f[i]);
   }
 
   // one face value: fixed stencil over the fbar+ ring (Eqs. 24-26); the
@@ -272,17 +274,18 @@ struct Marcher {
       out[6] += (a2 - ax2) - ay2;
       out[4] += (a2 - ax2) + ay2;
     }
-    // f~+ = (4 fbar+ - f~) / 3, then f~^{n+1} = f~+ + dt L (Eqs. 9, 23, 21);
-    // f~ of row k is read again here (cache hit) rather than held in registers
-    // across the two rows of the pipeline
-    const T four3 = T(4) / T(3), third = T(1) / T(3);
+    // f~+ = fbar+ + (fbar+ - f~) / 3, then f~^{n+1} = f~+ + dt L (Eqs. 9, 23,
+    // 21); f~ of row k is read again here (cache hit) rather than held in
+    // registers across the two rows of the pipeline
+    const T third = T(1) / T(3);
     if (owned) {
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
       const T* p = row_src(kk);
 #pragma unroll
       for (int i = 0; i < 9; i++) {
-        const T tfp = fma(four3, bfp[slotB(k)][i][L], -(third * p[i * OWN]));
+        const T bp = bfp[slotB(k)][i][L];
+        const T tfp = fma(third, bp - p[i * OWN], bp);
         __builtin_nontemporal_store(tfp + out[i], o + i * OWN);
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
