@@ -12,9 +12,11 @@
  * Conventions
  *  - Every call returns a dugks_status; nothing is thrown and nothing aborts.
  *    dugks_strerror() gives a static text for each code.
- *  - The library owns only the plan (host memory).  Device memory is owned by
- *    the caller: it allocates dugks_state_bytes() bytes (256-byte aligned) and
- *    passes the pointer.  The library never allocates or frees device memory.
+ *  - The library owns the plan (host memory, and a small pinned host copy of
+ *    the state's constant head made by the first dugks_init).  Device memory
+ *    for states is owned by the caller: it allocates dugks_state_bytes() bytes
+ *    (256-byte aligned) and passes the pointer.  Batches (below) own a small
+ *    device allocation of their own for slot descriptors and the work list.
  *  - Streams are the caller's (hipStream_t passed as void*; NULL = default
  *    stream).  Calls that launch work are asynchronous on that stream; device
  *    faults surface at the caller's next synchronisation.
@@ -22,9 +24,12 @@
  *    call that depends on it (which of the two ping-pong buffers is current,
  *    the time t_n = n dt of the velocity field, and the zero d(phi u)/dt of the
  *    first step).
- *  - Layout in the state: f~ as 9 velocity-major planes [i][y][x], x
- *    contiguous with a row pitch, twice (ping-pong); the phi history plane twice;
- *    a small header, coefficient and velocity tables and mass scratch.
+ *  - Layout in the state: a 256-byte header, the face-stencil and velocity
+ *    tables, two ping-pong buffers and mass scratch.  A buffer holds the grid
+ *    in strips of 58 columns (the columns one 64-lane wavefront owns); row y
+ *    of a strip is one chunk of 10 planes of 58 elements -- f~_0..f~_8 and the
+ *    phi of the previous step -- padded to whole 128-byte lines.  Callers read
+ *    the state only through dugks_phi / dugks_distributions / dugks_mass.
  *  - Plans are immutable after creation and may be shared between threads;
  *    calls on distinct states may run concurrently on distinct streams.
  *    Calls on one state must be ordered by the caller.
@@ -81,6 +86,14 @@ typedef enum {
 
 /* flags */
 #define DUGKS_FLAG_DTPHIU_ZERO 1u /* drop d(phi u)/dt from the source (test hook) */
+/* Fused mass correction (meant for FP32 plans): every step also sums
+ * phi^{n+1} in FP64 (per 8-row group of each strip, then a fixed-order
+ * Neumaier reduction) and records delta = (M0 - M^{n+1}) / (nx ny); the next
+ * step adds w_i delta to each f~_i as it loads it.  dugks_phi,
+ * dugks_distributions and dugks_mass include the pending delta.  Segments of
+ * such plans are whole 8-row groups (tile_rows is rounded up), so results
+ * stay independent of the tiling. */
+#define DUGKS_FLAG_MASS_FIX 2u
 
 typedef struct {
   int32_t nx, ny;          /* cells per side, periodic; each in [8, 65536]         */
@@ -110,9 +123,11 @@ size_t dugks_state_bytes(const dugks_plan *plan);
 
 /* Write the first state (step 0) from phi0 (device, FP64, [ny][nx] dense):
  * f~^0 = feq(phi0, u(x, 0)) - (dt/2) S^0 with d(phi u)/dt = 0, and the
- * coefficient and velocity tables of the plan.  Blocks the calling thread
- * until the work queued on `stream` is done (the tables are staged from host
- * memory).  Errors: EINVAL (NULL, misaligned state), EDEVICE. */
+ * coefficient and velocity tables of the plan, and record M0 = sum phi0 (FP64).
+ * Asynchronous on `stream`.  The first call on a plan stages the tables in
+ * pinned host memory the plan keeps until dugks_plan_destroy, which must not
+ * run before the copy has executed.  Errors: EINVAL (NULL, misaligned state),
+ * EDEVICE. */
 int dugks_init(const dugks_plan *plan, void *state, const double *phi0_dev,
                void *stream);
 
@@ -145,13 +160,79 @@ int dugks_mass(const dugks_plan *plan, void *state, int64_t step,
 /* FP32 plans: measure the mass of the state at `step` as dugks_mass does and
  * add w_i * (M0 - M) / (nx ny) to every f~_i, M0 being the mass of phi0 in
  * FP64 recorded by dugks_init.  The correction's own rounding is measured and
- * corrected once more.  FP64 plans: no-op.  Asynchronous. */
+ * corrected once more.  FP64 plans and plans with DUGKS_FLAG_MASS_FIX (which
+ * correct every step): no-op.  Asynchronous. */
 int dugks_mass_correct(const dugks_plan *plan, void *state, int64_t step,
                        void *stream);
 
 /* Initial mass M0 (FP64) recorded by dugks_init, copied to *out_dev. */
 int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
                 void *stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent grids advanced together, as the serving and batched forms
+ * need them: a batch has `capacity` slots, each holding a (plan, state) pair
+ * of the batch's precision and reconstruction, the step the state is at and
+ * the step to stop at.  One persistent kernel takes the tiles of every active
+ * grid from a work list in device memory (taller tiles first); a second, tiny
+ * kernel then advances each active slot's step counter (and applies the fused
+ * mass correction of DUGKS_FLAG_MASS_FIX batches).  Results are bitwise those
+ * of dugks_step on the same plan and state.
+ *  - The batch allocates a small amount of device memory of its own (slot
+ *    descriptors, step counters, work list) on the device current at
+ *    dugks_batch_create; every later call expects that device to be current.
+ *  - set / clear change the host copy; dugks_batch_commit uploads it
+ *    (asynchronously, ordered on `stream`) and must come before the next
+ *    dugks_batch_step.  States must stay allocated while a slot holds them.
+ *  - The step counters are the batch's while a state is attached: read them
+ *    with dugks_batch_steps.
+ *  - A batch is not thread-safe; calls on one batch must be serialised. */
+typedef struct dugks_batch dugks_batch;
+
+/* Create a batch of `capacity` slots (1..65536), all empty.  flags: 0 or
+ * DUGKS_FLAG_MASS_FIX (then every attached plan must carry it, else none may).
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon,
+                       uint32_t flags, dugks_batch **out);
+/* Wait for the device, then free the batch and its device memory. */
+void dugks_batch_destroy(dugks_batch *batch);
+
+/* Attach `state` (initialised by dugks_init for `plan`, currently at `step`)
+ * to `slot`; the grid advances until its counter reaches `target` (>= step).
+ * Replaces whatever the slot held.  Errors: EINVAL (range, NULL, misaligned
+ * state, plan of another precision / reconstruction / mass-fix flag). */
+int dugks_batch_set(dugks_batch *batch, int32_t slot, const dugks_plan *plan,
+                    void *state, int64_t step, int64_t target);
+/* Empty `slot`.  Errors: EINVAL. */
+int dugks_batch_clear(dugks_batch *batch, int32_t slot);
+/* Upload slot descriptors, changed step counters and the work list.
+ * Asynchronous on `stream` (pinned staging; may wait for an older upload).
+ * Errors: EINVAL, EDEVICE. */
+int dugks_batch_commit(dugks_batch *batch, void *stream);
+/* Run `nsteps` batch steps on `stream`: each active slot advances by one step
+ * per batch step until it reaches its target.  With graph_steps > 1, whole
+ * groups of graph_steps steps replay one captured hipGraph (captured on first
+ * use for that group size); the rest are launched directly.  Asynchronous.
+ * Errors: EINVAL (nsteps < 0, graph_steps outside 0..4096), EDEVICE. */
+int dugks_batch_step(dugks_batch *batch, int64_t nsteps, int32_t graph_steps,
+                     void *stream);
+/* Copy the per-slot (step, target) pairs, int64[2 * capacity], to `out`
+ * (host or device memory; asynchronous on `stream` when `out` is pinned or on
+ * the device).  Errors: EINVAL, EDEVICE. */
+int dugks_batch_steps(const dugks_batch *batch, int64_t *out, void *stream);
+/* Rows per tile of every grid (a multiple of 8; grids shorter than that are
+ * one tile high).  Default 64.  set: EINVAL unless 8 <= rows <= 65536 and
+ * rows % 8 == 0; takes effect at the next commit. */
+int dugks_batch_tile_rows(const dugks_batch *batch);
+int dugks_batch_set_tile_rows(dugks_batch *batch, int32_t rows);
+/* Autotuner: time the persistent step kernel over the attached, active grids
+ * (`reps` launches per candidate tile height from 16 to 256 rows, HIP events
+ * on `stream`), keep the fastest and commit it.  The timed launches write only
+ * each grid's next-step buffer and mass partials, which the next real step
+ * overwrites, so the states and results are unchanged.  Blocks until done.
+ * Errors: EINVAL, EDEVICE. */
+int dugks_batch_tune(dugks_batch *batch, int32_t reps, int32_t *rows_out,
+                     void *stream);
 
 const char *dugks_strerror(int status);
 

@@ -20,6 +20,7 @@ F64, F32 = 0, 1
 CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
 FLAG_DTPHIU_ZERO = 1
+FLAG_MASS_FIX = 2
 
 
 class DugksError(RuntimeError):
@@ -68,9 +69,24 @@ def load() -> ctypes.CDLL:
     L.dugks_strerror.argtypes = [ctypes.c_int]
     L.dugks_strerror.restype = ctypes.c_char_p
     L.dugks_version.restype = ctypes.c_char_p
+    L.dugks_batch_create.argtypes = [i32, i32, i32, ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.dugks_batch_destroy.argtypes = [vp]
+    L.dugks_batch_destroy.restype = None
+    L.dugks_batch_set.argtypes = [vp, i32, vp, vp, i64, i64]
+    L.dugks_batch_clear.argtypes = [vp, i32]
+    L.dugks_batch_commit.argtypes = [vp, vp]
+    L.dugks_batch_step.argtypes = [vp, i64, i32, vp]
+    L.dugks_batch_steps.argtypes = [vp, vp, vp]
+    L.dugks_batch_tile_rows.argtypes = [vp]
+    L.dugks_batch_set_tile_rows.argtypes = [vp, i32]
+    L.dugks_batch_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     for name in ("dugks_plan_create", "dugks_init", "dugks_step", "dugks_phi",
                  "dugks_distributions",
-                 "dugks_mass", "dugks_mass_correct", "dugks_mass0"):
+                 "dugks_mass", "dugks_mass_correct", "dugks_mass0",
+                 "dugks_batch_create", "dugks_batch_set", "dugks_batch_clear",
+                 "dugks_batch_commit", "dugks_batch_step", "dugks_batch_steps",
+                 "dugks_batch_tile_rows", "dugks_batch_set_tile_rows",
+                 "dugks_batch_tune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -157,6 +173,52 @@ def dugks_mass_correct(plan: int, state: int, step: int, stream: int) -> None:
 
 def dugks_mass0(plan: int, state: int, out_dev: int, stream: int) -> None:
     _check(load().dugks_mass0(plan, state, out_dev, stream), "dugks_mass0")
+
+
+def dugks_batch_create(capacity: int, precision: int, recon: int, flags: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check(load().dugks_batch_create(capacity, precision, recon, flags, ctypes.byref(out)),
+           "dugks_batch_create")
+    return out.value
+
+
+def dugks_batch_destroy(batch: int) -> None:
+    load().dugks_batch_destroy(batch)
+
+
+def dugks_batch_set(batch: int, slot: int, plan: int, state: int, step: int,
+                    target: int) -> None:
+    _check(load().dugks_batch_set(batch, slot, plan, state, step, target), "dugks_batch_set")
+
+
+def dugks_batch_clear(batch: int, slot: int) -> None:
+    _check(load().dugks_batch_clear(batch, slot), "dugks_batch_clear")
+
+
+def dugks_batch_commit(batch: int, stream: int) -> None:
+    _check(load().dugks_batch_commit(batch, stream), "dugks_batch_commit")
+
+
+def dugks_batch_step(batch: int, nsteps: int, graph_steps: int, stream: int) -> None:
+    _check(load().dugks_batch_step(batch, nsteps, graph_steps, stream), "dugks_batch_step")
+
+
+def dugks_batch_steps(batch: int, out: int, stream: int) -> None:
+    _check(load().dugks_batch_steps(batch, out, stream), "dugks_batch_steps")
+
+
+def dugks_batch_tile_rows(batch: int) -> int:
+    return load().dugks_batch_tile_rows(batch)
+
+
+def dugks_batch_set_tile_rows(batch: int, rows: int) -> None:
+    _check(load().dugks_batch_set_tile_rows(batch, rows), "dugks_batch_set_tile_rows")
+
+
+def dugks_batch_tune(batch: int, reps: int, stream: int) -> int:
+    rows = ctypes.c_int32()
+    _check(load().dugks_batch_tune(batch, reps, ctypes.byref(rows), stream), "dugks_batch_tune")
+    return rows.value
 
 
 def dugks_strerror(code: int) -> str:

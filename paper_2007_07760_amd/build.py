@@ -11,8 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdugks.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dugks_abi.hip"]
-HEADERS = ["dugks_common.h", "dugks_kernels.h"]
+SOURCES = ["dugks_abi.hip", "dugks_batch.hip"]
+HEADERS = ["dugks_common.h", "dugks_kernels.h", "dugks_plan.h"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

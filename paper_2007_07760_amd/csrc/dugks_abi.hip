@@ -5,25 +5,15 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "dugks_common.h"
 #include "dugks_kernels.h"
+#include "dugks_plan.h"
 
 using namespace dugks;
-
-struct dugks_plan {
-  dugks_params p;
-  Layout L;
-  double coef[2][9][NTAP];   // face stencils (Eqs. 25-26)
-  double compact[NCOMPACT];  // the same, folded by the lattice symmetries
-  double dt, h, tau;
-  double cA, cB, cA2, cB2, alpha, beta, gamma;
-  double period;             // cos(pi t / period) modulation; 0 = steady
-  int seg_rows, nstrips, nsegs;
-  std::vector<double> tabx, taby;
-};
 
 namespace {
 
@@ -194,7 +184,7 @@ int validate(const dugks_params* p) {
   if (p->recon < 0 || p->recon > 2) return DUGKS_EINVAL;
   if (p->precision < 0 || p->precision > 1) return DUGKS_EINVAL;
   if (p->vel_kind < 0 || p->vel_kind > 4) return DUGKS_EINVAL;
-  if (p->flags & ~DUGKS_FLAG_DTPHIU_ZERO) return DUGKS_EINVAL;
+  if (p->flags & ~(DUGKS_FLAG_DTPHIU_ZERO | DUGKS_FLAG_MASS_FIX)) return DUGKS_EINVAL;
   if (p->tile_rows < 0 || p->tile_rows > 65536 || p->reserved != 0) return DUGKS_EINVAL;
   for (int k = 0; k < 6; k++)
     if (!finite(p->vel_param[k])) return DUGKS_EINVAL;
@@ -205,21 +195,19 @@ int validate(const dugks_params* p) {
   return DUGKS_OK;
 }
 
-bool aligned(const void* ptr) { return ((uintptr_t)ptr & 255u) == 0; }
-
 // Default rows per wavefront.  Resident wavefronts of the step kernel on one
 // MI355X (256 CUs; per CU 8 in FP64 and 16 in FP32, limited by the LDS ring and
 // registers, 6/12 for the 5-row ring of central-4).  A wavefront marches
 // seg + 4 rows of work; the launch runs in ceil(tiles / resident) rounds, so
 // pick the segment that minimises rounds * (seg + 4): whole rounds, little
-// halo.  The autotuner replaces this by measurement.
+// halo.  Segments are whole mass groups (multiples of MASS_GROUP rows).
 int default_tile_rows(const dugks_params& p, int nstrips) {
   const bool c4 = p.recon == DUGKS_CENTRAL4;
   const int per_cu = p.precision == DUGKS_F64 ? (c4 ? 6 : 8) : (c4 ? 12 : 16);
   const long resident = 256L * per_cu;
   int best = 64;
   long best_cost = -1;
-  for (int seg = 16; seg <= 256; seg += 4) {
+  for (int seg = 16; seg <= 256; seg += MASS_GROUP) {
     const long tiles = (long)nstrips * ((p.ny + seg - 1) / seg);
     const long rounds = (tiles + resident - 1) / resident;
     const long cost = rounds * (long)(std::min(seg, p.ny) + 4);
@@ -231,100 +219,69 @@ int default_tile_rows(const dugks_params& p, int nstrips) {
   return best;
 }
 
-int hip_status(hipError_t e) { return e == hipSuccess ? DUGKS_OK : DUGKS_EDEVICE; }
-
-template <typename T>
-T* at(void* state, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(state) + off);
-}
-template <typename T>
-const T* at(const void* state, size_t off) {
-  return reinterpret_cast<const T*>(static_cast<const char*>(state) + off);
-}
-
 // ------------------------------------------------------------ launches
-template <typename T>
-StepBufs<T> step_bufs(const dugks_plan* P, void* state, int64_t n) {
+template <typename T, bool MFIX>
+int launch_step_t(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
   const Layout& L = P->L;
-  const int b = (int)(n & 1);
-  StepBufs<T> q;
-  q.src = at<T>(state, L.off_buf[b]);
-  q.dst = at<T>(state, L.off_buf[b ^ 1]);
-  q.cf = at<T>(state, L.off_coef);
-  q.tabx = at<T>(state, L.off_tabx);
-  q.taby = at<T>(state, L.off_taby);
-  return q;
-}
-
-template <typename T>
-StepArgs<T> step_args(const dugks_plan* P) {
-  const Layout& L = P->L;
-  StepArgs<T> a;
-  a.CH = L.tl.CH;
-  a.nx = P->p.nx;
-  a.ny = P->p.ny;
-  a.seg_rows = P->seg_rows;
-  a.nstrips = P->nstrips;
-  a.nsegs = P->nsegs;
-  a.nlogical = P->nstrips * P->nsegs;
-  a.cB2 = T(P->cB2);
-  a.pscale = T(P->beta / P->alpha);
-  a.gdt = T(0.5 * P->dt * P->gamma);
-  a.dt = T(P->dt);
-  a.tau = T(P->tau);
-  a.kth = isfinite(P->p.width) ? T(4.0 / P->p.width) : T(0);
-  a.period = P->period;
-  a.dtd = P->dt;
-  a.hd = P->h;
-  a.jzero = (P->p.flags & DUGKS_FLAG_DTPHIU_ZERO) ? 1 : 0;
-  return a;
-}
-
-template <typename T>
-int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
   StepArgs<T> a = step_args<T>(P);
   StepBufs<T> q = step_bufs<T>(P, state, n);
+  double* part = at<double>(state, L.off_groups);
+  StateHeader* hd = at<StateHeader>(state, 0);
   const int per = (a.nlogical + 7) / 8;
   dim3 grid(per * 8), block(LANES);
-#define DUGKS_LAUNCH(RR)                                                                   \
-  hipLaunchKernelGGL((step_kernel<T, RR>), grid, block, 0, s, a, n, q.src, q.dst, q.cf, q.tabx, \
-                     q.taby)
+#define DUGKS_LAUNCH(RR)                                                                      \
+  hipLaunchKernelGGL((step_kernel<T, RR, MFIX>), grid, block, 0, s, a, n, q.src, q.dst, q.cf, \
+                     q.tabx, q.taby, part, hd)
   switch (P->p.recon) {
     case DUGKS_CENTRAL2: DUGKS_LAUNCH(DUGKS_CENTRAL2); break;
     case DUGKS_UPWIND3: DUGKS_LAUNCH(DUGKS_UPWIND3); break;
     default: DUGKS_LAUNCH(DUGKS_CENTRAL4); break;
   }
 #undef DUGKS_LAUNCH
+  if (MFIX)
+    hipLaunchKernelGGL(mass_fix_kernel, dim3(1), dim3(MASS_THREADS), 0, s, part,
+                       L.tl.nstrips * L.ngroups, hd, (double)P->p.nx * (double)P->p.ny);
   return hip_status(hipGetLastError());
+}
+
+template <typename T>
+int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+  return (P->p.flags & DUGKS_FLAG_MASS_FIX) ? launch_step_t<T, true>(P, state, n, s)
+                                           : launch_step_t<T, false>(P, state, n, s);
+}
+
+template <typename T>
+int stage_head(const dugks_plan* P) {
+  const Layout& L = P->L;
+  void* h = nullptr;
+  if (hipHostMalloc(&h, L.off_buf[0], hipHostMallocDefault) != hipSuccess) return DUGKS_EDEVICE;
+  memset(h, 0, L.off_buf[0]);
+  StateHeader* hd = static_cast<StateHeader*>(h);
+  hd->magic = STATE_MAGIC;
+  hd->nx = P->p.nx;
+  hd->ny = P->p.ny;
+  hd->precision = P->p.precision;
+  hd->recon = P->p.recon;
+  hd->sigma = 1.0;
+  // the device table carries dt * alpha (Eq. 27) times the stencil
+  T* cf = at<T>(h, L.off_coef);
+  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->alpha * P->compact[k]);
+  T* tx = at<T>(h, L.off_tabx);
+  for (size_t k = 0; k < P->tabx.size(); k++) tx[k] = T(P->tabx[k]);
+  T* ty = at<T>(h, L.off_taby);
+  for (size_t k = 0; k < P->taby.size(); k++) ty[k] = T(P->taby[k]);
+  P->head = h;
+  return DUGKS_OK;
 }
 
 template <typename T>
 int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s) {
   const Layout& L = P->L;
   const int nx = P->p.nx, ny = P->p.ny;
-  // header, coefficients and velocity tables in the state's precision
-  StateHeader h;
-  memset(&h, 0, sizeof(h));
-  h.magic = STATE_MAGIC;
-  h.nx = nx;
-  h.ny = ny;
-  h.precision = P->p.precision;
-  h.recon = P->p.recon;
-  // the device table carries dt * alpha (Eq. 27) times the stencil
-  std::vector<T> cf(NCOMPACT), tx(P->tabx.size()), ty(P->taby.size());
-  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->alpha * P->compact[k]);
-  for (size_t k = 0; k < tx.size(); k++) tx[k] = T(P->tabx[k]);
-  for (size_t k = 0; k < ty.size(); k++) ty[k] = T(P->taby[k]);
+  std::call_once(P->staged, [P] { P->head_rc = stage_head<T>(P); });
+  if (P->head_rc) return P->head_rc;
   hipError_t e;
-  if ((e = hipMemcpyAsync(state, &h, sizeof(h), hipMemcpyHostToDevice, s))) return hip_status(e);
-  if ((e = hipMemcpyAsync(at<T>(state, L.off_coef), cf.data(), cf.size() * sizeof(T),
-                          hipMemcpyHostToDevice, s)))
-    return hip_status(e);
-  if ((e = hipMemcpyAsync(at<T>(state, L.off_tabx), tx.data(), tx.size() * sizeof(T),
-                          hipMemcpyHostToDevice, s)))
-    return hip_status(e);
-  if ((e = hipMemcpyAsync(at<T>(state, L.off_taby), ty.data(), ty.size() * sizeof(T),
-                          hipMemcpyHostToDevice, s)))
+  if ((e = hipMemcpyAsync(state, P->head, L.off_buf[0], hipMemcpyHostToDevice, s)))
     return hip_status(e);
   InitArgs<T> a;
   a.phi0 = phi0;
@@ -341,12 +298,10 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   double* part = at<double>(state, L.off_scratch);
   StateHeader* hd = at<StateHeader>(state, 0);
   hipLaunchKernelGGL((mass_partial_kernel<double, false>), dim3(MASS_BLOCKS), dim3(MASS_THREADS),
-                     0, s, phi0, L.tl, part);
+                     0, s, phi0, L.tl, nullptr, part);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass0,
                      &hd->mass_now);
-  if ((e = hipGetLastError())) return hip_status(e);
-  // the host staging vectors must outlive the copies
-  return hip_status(hipStreamSynchronize(s));
+  return hip_status(hipGetLastError());
 }
 
 template <typename T>
@@ -355,7 +310,7 @@ int do_phi(const dugks_plan* P, const void* state, int64_t n, void* out, hipStre
   const int nx = P->p.nx, ny = P->p.ny;
   dim3 grid((nx + 255) / 256, ny), block(256);
   hipLaunchKernelGGL((phi_kernel<T>), grid, block, 0, s, at<T>(state, L.off_buf[n & 1]), L.tl,
-                     static_cast<T*>(out));
+                     at<StateHeader>(state, 0), static_cast<T*>(out));
   return hip_status(hipGetLastError());
 }
 
@@ -365,7 +320,7 @@ int do_export(const dugks_plan* P, const void* state, int64_t n, void* out, hipS
   const int nx = P->p.nx, ny = P->p.ny;
   dim3 grid((nx + 255) / 256, ny, 9), block(256);
   hipLaunchKernelGGL((export_kernel<T>), grid, block, 0, s, at<T>(state, L.off_buf[n & 1]), L.tl,
-                     static_cast<T*>(out));
+                     at<StateHeader>(state, 0), static_cast<T*>(out));
   return hip_status(hipGetLastError());
 }
 
@@ -375,7 +330,7 @@ int do_mass(const dugks_plan* P, void* state, int64_t n, double* out, hipStream_
   double* part = at<double>(state, L.off_scratch);
   StateHeader* hd = at<StateHeader>(state, 0);
   hipLaunchKernelGGL((mass_partial_kernel<T, true>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
-                     at<T>(state, L.off_buf[n & 1]), L.tl, part);
+                     at<T>(state, L.off_buf[n & 1]), L.tl, hd, part);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass_now, out);
   return hip_status(hipGetLastError());
 }
@@ -431,13 +386,19 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
   make_tables(P);
   P->nstrips = (p->nx + OWN - 1) / OWN;
   P->seg_rows = p->tile_rows > 0 ? p->tile_rows : default_tile_rows(*p, P->nstrips);
+  if (p->flags & DUGKS_FLAG_MASS_FIX)   // whole mass groups per segment
+    P->seg_rows = (P->seg_rows + MASS_GROUP - 1) / MASS_GROUP * MASS_GROUP;
   if (P->seg_rows > p->ny) P->seg_rows = p->ny;
   P->nsegs = (p->ny + P->seg_rows - 1) / P->seg_rows;
   *out = P;
   return DUGKS_OK;
 }
 
-void dugks_plan_destroy(dugks_plan* plan) { delete plan; }
+void dugks_plan_destroy(dugks_plan* plan) {
+  if (!plan) return;
+  if (plan->head) (void)hipHostFree(plan->head);
+  delete plan;
+}
 
 size_t dugks_state_bytes(const dugks_plan* plan) { return plan ? plan->L.total : 0; }
 
@@ -486,7 +447,7 @@ int dugks_mass(const dugks_plan* plan, void* state, int64_t step, double* mass_o
 
 int dugks_mass_correct(const dugks_plan* plan, void* state, int64_t step, void* stream) {
   if (!plan || !state || !aligned(state) || step < 0) return DUGKS_EINVAL;
-  if (plan->p.precision == DUGKS_F64) return DUGKS_OK;
+  if (plan->p.precision == DUGKS_F64 || (plan->p.flags & DUGKS_FLAG_MASS_FIX)) return DUGKS_OK;
   return do_correct<float>(plan, state, step, static_cast<hipStream_t>(stream));
 }
 

@@ -1,0 +1,467 @@
+// dugks_batch.hip -- C ABI of batches (include/dugks.h): many independent
+// grids of one precision and reconstruction advanced by one persistent kernel,
+// replayed from a captured hipGraph, with a measured choice of tile height.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "dugks_common.h"
+#include "dugks_kernels.h"
+#include "dugks_plan.h"
+
+using namespace dugks;
+
+namespace {
+
+constexpr int NSTAGE = 3;   // pinned staging buffers in flight
+
+// Tile heights the autotuner tries (whole mass groups).
+constexpr int TUNE_ROWS[] = {16, 24, 32, 48, 64, 96, 128, 192, 256};
+constexpr int DEFAULT_ROWS = 64;
+
+struct Slot {
+  const dugks_plan* plan = nullptr;
+  void* state = nullptr;
+  int64_t step = 0, target = 0;
+  bool step_dirty = false;
+};
+
+}  // namespace
+
+struct dugks_batch {
+  int cap = 0, precision = 0, recon = 0;
+  bool mfix = false;
+  int device = 0;
+  size_t desc_bytes = 0;              // sizeof(GridDesc<T>)
+  // device memory owned by the batch
+  void* d_desc = nullptr;             // GridDesc<T>[cap]
+  SlotStep* d_steps = nullptr;        // [cap]
+  BatchCtl* d_ctl = nullptr;
+  unsigned* d_head = nullptr;
+  BatchItem* d_items = nullptr;
+  size_t items_cap = 0;
+  // host side
+  std::vector<Slot> slots;
+  std::vector<BatchItem> items;
+  bool desc_dirty = true;
+  int rows = DEFAULT_ROWS;            // tile height (rows per item)
+  int grid_blocks = 0;                // resident wavefronts of the persistent kernel
+  // pinned staging ring: [ctl][desc table][steps][items]
+  void* stage[NSTAGE] = {};
+  size_t stage_bytes[NSTAGE] = {};
+  hipEvent_t stage_ev[NSTAGE] = {};
+  int stage_next = 0;
+  // graph of K steps
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_k = 0;
+};
+
+namespace {
+
+template <typename T>
+GridDesc<T> make_desc(const Slot& s, int rows) {
+  GridDesc<T> d;
+  memset(&d, 0, sizeof(d));
+  if (!s.plan) return d;
+  const dugks_plan* P = s.plan;
+  const Layout& L = P->L;
+  d.a = step_args<T>(P);
+  const int seg = std::min(rows, P->p.ny);
+  d.a.seg_rows = seg;
+  d.a.nsegs = (P->p.ny + seg - 1) / seg;
+  d.a.nlogical = d.a.nstrips * d.a.nsegs;
+  d.buf[0] = at<T>(s.state, L.off_buf[0]);
+  d.buf[1] = at<T>(s.state, L.off_buf[1]);
+  d.cf = at<T>(s.state, L.off_coef);
+  d.tabx = at<T>(s.state, L.off_tabx);
+  d.taby = at<T>(s.state, L.off_taby);
+  d.hdr = at<StateHeader>(s.state, 0);
+  d.part = at<double>(s.state, L.off_groups);
+  d.ncells = (double)P->p.nx * (double)P->p.ny;
+  d.ngroups = L.tl.nstrips * L.ngroups;
+  return d;
+}
+
+// Work list for tile height `rows`: every tile of every attached slot, the
+// taller tiles first so that the short ones fill the tail of the step.
+void build_items(dugks_batch* B, int rows) {
+  B->items.clear();
+  struct Keyed {
+    int h;
+    BatchItem it;
+  };
+  std::vector<Keyed> v;
+  for (int k = 0; k < B->cap; k++) {
+    const Slot& s = B->slots[k];
+    if (!s.plan) continue;
+    const int ny = s.plan->p.ny, nstrips = s.plan->nstrips;
+    const int seg = std::min(rows, ny);
+    const int nsegs = (ny + seg - 1) / seg;
+    for (int g = 0; g < nsegs; g++) {
+      const int h = std::min(seg, ny - g * seg);
+      for (int st = 0; st < nstrips; st++) v.push_back({h, {k, g * nstrips + st}});
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const Keyed& a, const Keyed& b) { return a.h > b.h; });
+  B->items.reserve(v.size());
+  for (const Keyed& k : v) B->items.push_back(k.it);
+}
+
+int ensure_items_cap(dugks_batch* B, size_t n, hipStream_t s) {
+  if (n <= B->items_cap) return DUGKS_OK;
+  // in-flight steps may still read the old list
+  if (hipStreamSynchronize(s) != hipSuccess) return DUGKS_EDEVICE;
+  if (B->d_items) (void)hipFree(B->d_items);
+  B->d_items = nullptr;
+  B->items_cap = 0;
+  size_t cap = std::max<size_t>(n, 2 * n);
+  if (hipMalloc(&B->d_items, cap * sizeof(BatchItem)) != hipSuccess) return DUGKS_EDEVICE;
+  B->items_cap = cap;
+  return DUGKS_OK;
+}
+
+// Copy the descriptor table, the changed step counters and the work list to
+// the device (asynchronous, through the pinned staging ring).
+template <typename T>
+int upload(dugks_batch* B, hipStream_t s) {
+  int rc = ensure_items_cap(B, std::max<size_t>(B->items.size(), 1), s);
+  if (rc) return rc;
+  const size_t off_desc = 256;
+  const size_t off_steps = align_up(off_desc + B->cap * sizeof(GridDesc<T>), 256);
+  const size_t off_items = align_up(off_steps + B->cap * sizeof(SlotStep), 256);
+  const size_t need = off_items + B->items.size() * sizeof(BatchItem);
+  const int j = B->stage_next;
+  B->stage_next = (j + 1) % NSTAGE;
+  if (hipEventSynchronize(B->stage_ev[j]) != hipSuccess) return DUGKS_EDEVICE;
+  if (B->stage_bytes[j] < need) {
+    if (B->stage[j]) (void)hipHostFree(B->stage[j]);
+    B->stage[j] = nullptr;
+    B->stage_bytes[j] = 0;
+    if (hipHostMalloc(&B->stage[j], 2 * need, hipHostMallocDefault) != hipSuccess)
+      return DUGKS_EDEVICE;
+    B->stage_bytes[j] = 2 * need;
+  }
+  char* h = static_cast<char*>(B->stage[j]);
+  BatchCtl* ctl = reinterpret_cast<BatchCtl*>(h);
+  ctl->items = B->d_items;
+  ctl->nitems = (int32_t)B->items.size();
+  ctl->pad = 0;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(B->d_ctl, ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s)))
+    return hip_status(e);
+  if (B->desc_dirty) {
+    GridDesc<T>* dt = reinterpret_cast<GridDesc<T>*>(h + off_desc);
+    for (int k = 0; k < B->cap; k++) dt[k] = make_desc<T>(B->slots[k], B->rows);
+    if ((e = hipMemcpyAsync(B->d_desc, dt, B->cap * sizeof(GridDesc<T>), hipMemcpyHostToDevice,
+                            s)))
+      return hip_status(e);
+    B->desc_dirty = false;
+  }
+  SlotStep* st = reinterpret_cast<SlotStep*>(h + off_steps);
+  for (int k = 0; k < B->cap; k++) {
+    Slot& sl = B->slots[k];
+    if (!sl.step_dirty) continue;
+    st[k].n = sl.step;
+    st[k].target = sl.target;
+    if ((e = hipMemcpyAsync(B->d_steps + k, st + k, sizeof(SlotStep), hipMemcpyHostToDevice, s)))
+      return hip_status(e);
+    sl.step_dirty = false;
+  }
+  if (!B->items.empty()) {
+    BatchItem* it = reinterpret_cast<BatchItem*>(h + off_items);
+    memcpy(it, B->items.data(), B->items.size() * sizeof(BatchItem));
+    if ((e = hipMemcpyAsync(B->d_items, it, B->items.size() * sizeof(BatchItem),
+                            hipMemcpyHostToDevice, s)))
+      return hip_status(e);
+  }
+  return hip_status(hipEventRecord(B->stage_ev[j], s));
+}
+
+template <typename T, int R, bool MFIX>
+int launch_batch_step(dugks_batch* B, hipStream_t s, bool finish) {
+  hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
+                     static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_ctl, B->d_head);
+  if (finish)
+    hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(B->cap), dim3(MASS_THREADS), 0, s,
+                       static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_head);
+  return hip_status(hipGetLastError());
+}
+
+// finish = false: the step kernel alone, which writes only the next-step
+// buffers and mass partials of each active slot (used to time tilings; the
+// state is unchanged, since the finish kernel never runs)
+int batch_launch(dugks_batch* B, hipStream_t s, bool finish) {
+#define DUGKS_BATCH(TT, RR)                                                    \
+  return B->mfix ? launch_batch_step<TT, RR, true>(B, s, finish)               \
+                 : launch_batch_step<TT, RR, false>(B, s, finish)
+#define DUGKS_BATCH_R(TT)                                        \
+  switch (B->recon) {                                            \
+    case DUGKS_CENTRAL2: DUGKS_BATCH(TT, DUGKS_CENTRAL2);        \
+    case DUGKS_UPWIND3: DUGKS_BATCH(TT, DUGKS_UPWIND3);          \
+    default: DUGKS_BATCH(TT, DUGKS_CENTRAL4);                    \
+  }
+  if (B->precision == DUGKS_F64) {
+    DUGKS_BATCH_R(double)
+  } else {
+    DUGKS_BATCH_R(float)
+  }
+#undef DUGKS_BATCH_R
+#undef DUGKS_BATCH
+}
+
+template <typename T, int R, bool MFIX>
+int occupancy(int* per_cu) {
+  return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX>), LANES, 0));
+}
+
+int batch_occupancy(const dugks_batch* B, int* per_cu) {
+#define DUGKS_OCC(TT, RR) \
+  return B->mfix ? occupancy<TT, RR, true>(per_cu) : occupancy<TT, RR, false>(per_cu)
+#define DUGKS_OCC_R(TT)                                 \
+  switch (B->recon) {                                   \
+    case DUGKS_CENTRAL2: DUGKS_OCC(TT, DUGKS_CENTRAL2);  \
+    case DUGKS_UPWIND3: DUGKS_OCC(TT, DUGKS_UPWIND3);    \
+    default: DUGKS_OCC(TT, DUGKS_CENTRAL4);              \
+  }
+  if (B->precision == DUGKS_F64) {
+    DUGKS_OCC_R(double)
+  } else {
+    DUGKS_OCC_R(float)
+  }
+#undef DUGKS_OCC_R
+#undef DUGKS_OCC
+}
+
+int commit(dugks_batch* B, hipStream_t s) {
+  build_items(B, B->rows);
+  return B->precision == DUGKS_F64 ? upload<double>(B, s) : upload<float>(B, s);
+}
+
+void release(dugks_batch* B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+  for (int j = 0; j < NSTAGE; j++) {
+    if (B->stage_ev[j]) {
+      (void)hipEventSynchronize(B->stage_ev[j]);
+      (void)hipEventDestroy(B->stage_ev[j]);
+    }
+    if (B->stage[j]) (void)hipHostFree(B->stage[j]);
+  }
+  if (B->d_items) (void)hipFree(B->d_items);
+  if (B->d_desc) (void)hipFree(B->d_desc);
+  if (B->d_steps) (void)hipFree(B->d_steps);
+  if (B->d_ctl) (void)hipFree(B->d_ctl);
+  if (B->d_head) (void)hipFree(B->d_head);
+}
+
+int capture_graph(dugks_batch* B, int k) {
+  if (B->exec && B->graph_k == k) return DUGKS_OK;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  if (hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return DUGKS_EDEVICE;
+  int rc = DUGKS_OK;
+  for (int j = 0; j < k && rc == DUGKS_OK; j++) rc = batch_launch(B, B->cap_stream, true);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+  if (rc || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return DUGKS_EDEVICE;
+  }
+  B->graph = g;
+  if (hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    B->exec = nullptr;
+    return DUGKS_EDEVICE;
+  }
+  B->graph_k = k;
+  return DUGKS_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint32_t flags,
+                       dugks_batch** out) {
+  if (!out) return DUGKS_EINVAL;
+  *out = nullptr;
+  if (capacity < 1 || capacity > 65536 || precision < 0 || precision > 1 || recon < 0 ||
+      recon > 2 || (flags & ~DUGKS_FLAG_MASS_FIX))
+    return DUGKS_EINVAL;
+  dugks_batch* B = new (std::nothrow) dugks_batch();
+  if (!B) return DUGKS_ENOMEM;
+  B->cap = capacity;
+  B->precision = precision;
+  B->recon = recon;
+  B->mfix = (flags & DUGKS_FLAG_MASS_FIX) != 0;
+  B->slots.resize(capacity);
+  B->desc_bytes = precision == DUGKS_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
+  int rc = DUGKS_OK;
+  int per_cu = 0, ncu = 0;
+  if (hipGetDevice(&B->device) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) !=
+          hipSuccess ||
+      (rc = batch_occupancy(B, &per_cu)) != DUGKS_OK || per_cu < 1 || ncu < 1 ||
+      hipMalloc(&B->d_desc, capacity * B->desc_bytes) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&B->d_steps), capacity * sizeof(SlotStep)) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&B->d_ctl), sizeof(BatchCtl)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&B->d_head), 256) != hipSuccess ||
+      hipMemset(B->d_desc, 0, capacity * B->desc_bytes) != hipSuccess ||
+      hipMemset(B->d_steps, 0, capacity * sizeof(SlotStep)) != hipSuccess ||
+      hipMemset(B->d_ctl, 0, sizeof(BatchCtl)) != hipSuccess ||
+      hipMemset(B->d_head, 0, 256) != hipSuccess ||
+      hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    release(B);
+    delete B;
+    return rc ? rc : DUGKS_EDEVICE;
+  }
+  for (int j = 0; j < NSTAGE; j++)
+    if (hipEventCreateWithFlags(&B->stage_ev[j], hipEventDisableTiming) != hipSuccess) {
+      release(B);
+      delete B;
+      return DUGKS_EDEVICE;
+    }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    release(B);
+    delete B;
+    return DUGKS_EDEVICE;
+  }
+  B->grid_blocks = per_cu * ncu;
+  *out = B;
+  return DUGKS_OK;
+}
+
+void dugks_batch_destroy(dugks_batch* batch) {
+  if (!batch) return;
+  (void)hipDeviceSynchronize();
+  release(batch);
+  delete batch;
+}
+
+int dugks_batch_set(dugks_batch* batch, int32_t slot, const dugks_plan* plan, void* state,
+                    int64_t step, int64_t target) {
+  if (!batch || slot < 0 || slot >= batch->cap || !plan || !state || !aligned(state) ||
+      step < 0 || target < step)
+    return DUGKS_EINVAL;
+  if (plan->p.precision != batch->precision || plan->p.recon != batch->recon ||
+      ((plan->p.flags & DUGKS_FLAG_MASS_FIX) != 0) != batch->mfix)
+    return DUGKS_EINVAL;
+  Slot& s = batch->slots[slot];
+  s.plan = plan;
+  s.state = state;
+  s.step = step;
+  s.target = target;
+  s.step_dirty = true;
+  batch->desc_dirty = true;
+  return DUGKS_OK;
+}
+
+int dugks_batch_clear(dugks_batch* batch, int32_t slot) {
+  if (!batch || slot < 0 || slot >= batch->cap) return DUGKS_EINVAL;
+  Slot& s = batch->slots[slot];
+  s = Slot();
+  s.step_dirty = true;   // (n, target) = (0, 0): idle
+  batch->desc_dirty = true;
+  return DUGKS_OK;
+}
+
+int dugks_batch_commit(dugks_batch* batch, void* stream) {
+  if (!batch) return DUGKS_EINVAL;
+  return commit(batch, static_cast<hipStream_t>(stream));
+}
+
+int dugks_batch_step(dugks_batch* batch, int64_t nsteps, int32_t graph_steps, void* stream) {
+  if (!batch || nsteps < 0 || graph_steps < 0 || graph_steps > 4096) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t left = nsteps;
+  if (graph_steps > 1 && nsteps >= graph_steps) {
+    int rc = capture_graph(batch, graph_steps);
+    if (rc) return rc;
+    for (; left >= graph_steps; left -= graph_steps)
+      if (hipGraphLaunch(batch->exec, s) != hipSuccess) return DUGKS_EDEVICE;
+  }
+  for (; left > 0; left--) {
+    int rc = batch_launch(batch, s, true);
+    if (rc) return rc;
+  }
+  return DUGKS_OK;
+}
+
+int dugks_batch_steps(const dugks_batch* batch, int64_t* out, void* stream) {
+  if (!batch || !out) return DUGKS_EINVAL;
+  return hip_status(hipMemcpyAsync(out, batch->d_steps, batch->cap * sizeof(SlotStep),
+                                   hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+}
+
+int dugks_batch_tile_rows(const dugks_batch* batch) { return batch ? batch->rows : -1; }
+
+int dugks_batch_set_tile_rows(dugks_batch* batch, int32_t rows) {
+  if (!batch || rows < MASS_GROUP || rows > 65536 || rows % MASS_GROUP) return DUGKS_EINVAL;
+  batch->rows = rows;
+  batch->desc_dirty = true;
+  return DUGKS_OK;
+}
+
+int dugks_batch_tune(dugks_batch* batch, int32_t reps, int32_t* rows_out, void* stream) {
+  if (!batch || reps < 1 || reps > 1000) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return DUGKS_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return DUGKS_EDEVICE;
+  }
+  int rc = DUGKS_OK;
+  float best_ms = -1.0f;
+  int best = batch->rows;
+  for (int rows : TUNE_ROWS) {
+    batch->rows = rows;
+    batch->desc_dirty = true;
+    if ((rc = commit(batch, s))) break;
+    // one untimed pass, then the timed passes
+    if ((rc = batch_launch(batch, s, false))) break;
+    // the step kernel alone leaves the queue head at its end: rewind it
+    if (hipMemsetAsync(batch->d_head, 0, sizeof(unsigned), s) != hipSuccess) {
+      rc = DUGKS_EDEVICE;
+      break;
+    }
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == DUGKS_OK; r++) {
+      rc = batch_launch(batch, s, false);
+      if (!rc && hipMemsetAsync(batch->d_head, 0, sizeof(unsigned), s) != hipSuccess)
+        rc = DUGKS_EDEVICE;
+    }
+    (void)hipEventRecord(e1, s);
+    if (rc || hipEventSynchronize(e1) != hipSuccess) {
+      rc = rc ? rc : DUGKS_EDEVICE;
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = rows;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch->rows = best;
+  batch->desc_dirty = true;
+  int rc2 = commit(batch, s);
+  if (!rc) rc = rc2;
+  if (!rc && rows_out) *rows_out = best;
+  return rc;
+}
+
+}  // extern "C"

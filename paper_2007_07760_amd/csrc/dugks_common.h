@@ -115,25 +115,32 @@ struct Tiling {
   }
 };
 
-// [header 256 B][coef table][x tables][y tables][buffer A][buffer B][scratch]
+// [header 256 B][coef table][x tables][y tables][buffer A][buffer B][mass scratch]
+// [row-group mass partials]
 struct StateHeader {
   uint64_t magic;
   double mass0;        // FP64 total of phi0
   double mass_now;     // last measured total
-  double delta;        // last correction per cell
+  double pending;      // fused correction: f~_i = stored f~_i + w_i pending
   int32_t nx, ny, precision, recon;
-  int64_t pad[26];
+  double mass_step;    // fused correction: M^n as the last step wrote it
+  double sigma;        // fused correction: fraction of delta that survives rounding
+  int64_t pad[24];
 };
 static_assert(sizeof(StateHeader) == 256, "header size");
 constexpr uint64_t STATE_MAGIC = 0x53474B5547554431ull;  // "1DUGUKGS"
 
 constexpr int MASS_BLOCKS = 256;   // fixed partial count: deterministic order
 constexpr int MASS_THREADS = 256;
+// The fused mass correction sums phi^{n+1} in groups of MASS_GROUP rows of one
+// strip; segments of such plans are whole groups.
+constexpr int MASS_GROUP = 8;
 
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)
   Tiling tl;
-  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, total;
+  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, off_groups, total;
+  int ngroups;         // row groups per strip
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -160,6 +167,9 @@ inline Layout make_layout(int nx, int ny, int precision) {
   }
   L.off_scratch = off;
   off = align_up(off + 2 * MASS_BLOCKS * sizeof(double) + 64, 256);
+  L.ngroups = (ny + MASS_GROUP - 1) / MASS_GROUP;
+  L.off_groups = off;
+  off = align_up(off + 2 * (size_t)L.tl.nstrips * L.ngroups * sizeof(double), 256);
   L.total = off;
   return L;
 }

@@ -30,6 +30,7 @@ struct StepArgs {
   int64_t CH;            // strip-chunk length (elements), see Tiling
   int nx, ny;
   int seg_rows, nstrips, nsegs, nlogical;
+  int ngroups;           // row groups of MASS_GROUP rows (mass partials)
   T cB2;                 // fbar+ = f~ + cB2 (feq + tau S - f~)
   T pscale;              // beta / alpha (the stencil table carries dt*alpha)
   T gdt;                 // dt * gamma / 2 (face S is the mean of two cells)
@@ -47,6 +48,30 @@ struct StepBufs {
   const T* __restrict__ tabx;    // UX[2nx+2], VX[2nx+2]
   const T* __restrict__ taby;    // UY[2ny+2], VY[2ny+2]
 };
+
+// Read-only tables that every lane of a wavefront reads at the same index
+// (the face stencil, the y velocity factors): read through the constant
+// address space, whose uniform loads go through the scalar cache into scalar
+// registers whatever the compiler can prove about aliasing with the stores.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+
+// copy of a struct read through the constant address space, word by word
+template <typename S>
+__device__ __forceinline__ S load_const(cptr<S> p) {
+  static_assert(sizeof(S) % 4 == 0, "whole words");
+  S v;
+  const cptr<uint32_t> w = (cptr<uint32_t>)p;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(S) / 4); k++) o[k] = w[k];
+  return v;
+}
 
 template <typename T>
 struct RowRegs {
@@ -89,16 +114,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int R>
+template <typename T, int R, bool MFIX>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
 
   const StepArgs<T>& a;
   const T* __restrict__ src;
   T* __restrict__ dst;
-  const T* __restrict__ cf;
+  cptr<T> cf;
   const T* __restrict__ tabx;
-  const T* __restrict__ taby;
+  cptr<T> taby;
   T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
   int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
@@ -113,6 +138,16 @@ struct Marcher {
   T sx0, sy0, sx1, sy1, sx2, sy2;  // s = theta n + J/RT of rows r-2 .. r
   T fS[9];                  // dt*alpha*fbar of the face below (north face of k-1)
   T PS, QSx, QSy;           // its collision part, see face_stage
+  // mass correction (MFIX): the stored f~_i lack w_i delta, delta being the
+  // per-cell correction set after the previous step; cw0..2 = w_i delta per
+  // weight class.  Per row group the lane sums the phi it writes (macc) and
+  // the corrected f~ it read (oacc, which tells how much of delta survived
+  // the rounding to T); the group totals go to part_row[2 group + 0 / 1].
+  T cw0, cw1, cw2;
+  double macc, oacc;
+  double* part_row;
+
+  __device__ __forceinline__ T cw(int i) const { return i == 0 ? cw0 : ((i & 1) ? cw1 : cw2); }
 
   __device__ __forceinline__ int slotB(int row) const { return (row - base) % RB; }
 
@@ -125,7 +160,7 @@ struct Marcher {
   __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
     const T* p = row_src(wrapi(row, a.ny));
 #pragma unroll
-    for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
+    for (int i = 0; i < 9; i++) d.f[i] = MFIX ? p[i * OWN] + cw(i) : p[i * OWN];
     d.hp = p[9 * OWN];
   }
 
@@ -232,8 +267,8 @@ struct Marcher {
       // LDS latency
       __builtin_amdgcn_sched_barrier(0);
     }
-    const T* UY = taby;
-    const T* VY = taby + (2 * a.ny + 2);
+    const cptr<T> UY = taby;
+    const cptr<T> VY = taby + (2 * a.ny + 2);
     // north face (x + 1/2, y + 1): S_b = mean of the two cells
     const T ubN = gH * (UXc * UY[2 * kk + 2]);
     const T vbN = gH * (VXc * VY[2 * kk + 2]);
@@ -278,6 +313,7 @@ struct Marcher {
     // 21); f~ of row k is read again here (cache hit) rather than held in
     // registers across the two rows of the pipeline
     const T third = T(1) / T(3);
+    double cs = 0.0, co = 0.0;
     if (owned) {
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
@@ -285,10 +321,37 @@ struct Marcher {
 #pragma unroll
       for (int i = 0; i < 9; i++) {
         const T bp = bfp[slotB(k)][i][L];
-        const T tfp = fma(third, bp - p[i * OWN], bp);
-        __builtin_nontemporal_store(tfp + out[i], o + i * OWN);
+        const T fo = MFIX ? p[i * OWN] + cw(i) : p[i * OWN];
+        const T tfp = fma(third, bp - fo, bp);
+        const T v = tfp + out[i];
+        __builtin_nontemporal_store(v, o + i * OWN);
+        if (MFIX) {
+          cs += (double)v;
+          co += (double)fo;
+        }
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
+    }
+    if (MFIX) {
+      // phi^{n+1} of the row into the group total; a group never straddles
+      // two segments (segments are whole groups), so its sum -- lanes in a
+      // fixed butterfly after rows in order -- does not depend on the tiling
+      macc += cs;
+      oacc += co;
+      if ((k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1) {
+        double v = macc, w = oacc;
+#pragma unroll
+        for (int m = 1; m < LANES; m <<= 1) {
+          v += __shfl_xor(v, m);
+          w += __shfl_xor(w, m);
+        }
+        if (lane == 0) {
+          part_row[2 * (k / MASS_GROUP)] = v;
+          part_row[2 * (k / MASS_GROUP) + 1] = w;
+        }
+        macc = 0.0;
+        oacc = 0.0;
+      }
     }
   }
 
@@ -306,6 +369,7 @@ struct Marcher {
 
   __device__ void run() {
     RowRegs<T> B, C;
+    macc = oacc = 0.0;
     ph0 = ph1 = ph2 = ph3 = T(0);
     D0 = D1 = D2 = A0 = A1 = A2 = T(0);
     sx0 = sy0 = sx1 = sy1 = sx2 = sy2 = T(0);
@@ -324,27 +388,18 @@ struct Marcher {
   }
 };
 
-template <typename T, int R>
-__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
-    StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
-    const T* __restrict__ cf, const T* __restrict__ tabx, const T* __restrict__ taby) {
-  constexpr int RB = Marcher<T, R>::RB;
-  __shared__ T s_bfp[RB][9][LROW];
-
-  // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
-  // each XCD a contiguous band of tiles (shared halos stay in one L2)
-  const int per = (a.nlogical + 7) >> 3;
-  const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (logical >= a.nlogical) return;
-  const int strip = logical % a.nstrips;
-  const int seg = logical / a.nstrips;
-
+// One tile: the strip `strip` of the grid, rows of segment `seg`, step n.
+// pend = per-cell mass correction delta still to apply to the stored f~ (MFIX).
+template <typename T, int R, bool MFIX>
+__device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
+                                           const T* __restrict__ src, T* __restrict__ dst,
+                                           const T* __restrict__ cf,
+                                           const T* __restrict__ tabx,
+                                           const T* __restrict__ taby,
+                                           double* __restrict__ part, double pend, int strip,
+                                           int seg, T (*s_bfp)[9][LROW]) {
+  Marcher<T, R, MFIX> m{a, src, dst, as_const(cf), tabx, as_const(taby), s_bfp};
   const int lane = threadIdx.x;
-  // the LDS pads are never read into owned results; keep them finite
-  for (int j = lane; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
-  __syncthreads();
-
-  Marcher<T, R> m{a, src, dst, cf, tabx, taby, s_bfp};
   const int x0 = strip * OWN;
   m.lane = lane;
   const int c0 = (x0 - HALO + lane) % a.nx;
@@ -375,7 +430,185 @@ __global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
   m.gP = T(gp);
   m.gH = T(gh);
   m.jscale = (n == 0 || a.jzero) ? T(0) : T(1) / a.dt;
+  if (MFIX) {
+    m.cw0 = T(wq(0) * pend);
+    m.cw1 = T(wq(1) * pend);
+    m.cw2 = T(wq(2) * pend);
+    m.part_row = part + 2 * (int64_t)strip * a.ngroups;
+  }
   m.run();
+}
+
+template <typename T, int R, bool MFIX>
+__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
+    StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
+    const T* __restrict__ cf, const T* __restrict__ tabx, const T* __restrict__ taby,
+    double* __restrict__ part, const StateHeader* __restrict__ hdr) {
+  constexpr int RB = Marcher<T, R, MFIX>::RB;
+  __shared__ T s_bfp[RB][9][LROW];
+
+  // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
+  // each XCD a contiguous band of tiles (shared halos stay in one L2)
+  const int per = (a.nlogical + 7) >> 3;
+  const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (logical >= a.nlogical) return;
+  const int strip = logical % a.nstrips;
+  const int seg = logical / a.nstrips;
+
+  // the LDS pads are never read into owned results; keep them finite
+  for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
+  __syncthreads();
+  const double pend = MFIX ? hdr->pending : 0.0;
+  march_tile<T, R, MFIX>(a, n, src, dst, cf, tabx, taby, part, pend, strip, seg, s_bfp);
+}
+
+// Neumaier pair (sum, compensation)
+__device__ __forceinline__ void neu_add(double& s, double& c, double v) {
+  double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+// After a step with the fused correction.  The partials hold, per row group,
+// the new total (M^{n+1}) and the total of the corrected f~^n the step read
+// (the mass the state really had after the last correction).  The part of the
+// last correction that survived the rounding of f~_i + w_i delta to T is
+// sigma = (that total - M^n) / (N delta); the next correction is
+// delta = (M0 - M^{n+1}) / (N sigma), so that what survives of it restores M0.
+// sigma keeps its last value while the correction is too small to measure.
+__device__ __forceinline__ void mass_fix_block(const double* __restrict__ part, int ngroups,
+                                               StateHeader* __restrict__ hdr, double ncells) {
+  __shared__ double ss[2][MASS_THREADS], sc[2][MASS_THREADS];
+  double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+  for (int j = threadIdx.x; j < ngroups; j += MASS_THREADS) {
+    neu_add(s[0], c[0], part[2 * j]);
+    neu_add(s[1], c[1], part[2 * j + 1]);
+  }
+  for (int q = 0; q < 2; q++) {
+    ss[q][threadIdx.x] = s[q];
+    sc[q][threadIdx.x] = c[q];
+  }
+  __syncthreads();
+  for (int w = MASS_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int q = 0; q < 2; q++) {
+        double a = ss[q][threadIdx.x], ac = sc[q][threadIdx.x] + sc[q][threadIdx.x + w];
+        neu_add(a, ac, ss[q][threadIdx.x + w]);
+        ss[q][threadIdx.x] = a;
+        sc[q][threadIdx.x] = ac;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m_new = ss[0][0] + sc[0][0];
+    const double m_read = ss[1][0] + sc[1][0];
+    const double applied = hdr->pending * ncells;
+    double sigma = hdr->sigma > 0.0 ? hdr->sigma : 1.0;
+    if (fabs(applied) > 1e-13 * fabs(hdr->mass0)) {
+      const double sv = (m_read - hdr->mass_step) / applied;
+      if (sv >= 0.0625 && sv <= 1.5) sigma = sv;
+    }
+    hdr->sigma = sigma;
+    hdr->mass_step = m_new;
+    hdr->mass_now = m_new;
+    hdr->pending = (hdr->mass0 - m_new) / (ncells * sigma);
+  }
+}
+
+static __global__ __launch_bounds__(MASS_THREADS) void mass_fix_kernel(
+    const double* __restrict__ part, int ngroups, StateHeader* __restrict__ hdr, double ncells) {
+  mass_fix_block(part, ngroups, hdr, ncells);
+}
+
+// ------------------------------------------------------------------ batch
+// Many independent grids (slots) advanced together by one persistent kernel.
+// Each slot has a descriptor (its scalars and buffers, written by the host when
+// the slot is attached) and a step counter pair (n, target) that the finish
+// kernel advances; a grid with n >= target is idle.  The work list holds one
+// item per (slot, tile) -- tile = seg * nstrips + strip, with the slot's own
+// segment height -- and wavefronts take items from a queue head in device
+// memory until the list is exhausted.
+template <typename T>
+struct GridDesc {
+  StepArgs<T> a;
+  T* buf[2];
+  const T* cf;
+  const T* tabx;
+  const T* taby;
+  StateHeader* hdr;
+  double* part;       // row-group partials of the fused mass correction
+  double ncells;
+  int ngroups;        // row groups over all strips (two partials each)
+  int pad;
+};
+
+struct SlotStep {
+  int64_t n;          // the step the slot's state is at
+  int64_t target;     // the slot stops once n reaches it
+};
+
+struct BatchItem {
+  int32_t slot, tile;
+};
+
+struct BatchCtl {
+  const BatchItem* items;
+  int32_t nitems;
+  int32_t pad;
+};
+
+template <typename T, int R, bool MFIX>
+__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void batch_step_kernel(
+    const GridDesc<T>* __restrict__ desc, const SlotStep* __restrict__ steps,
+    const BatchCtl* __restrict__ ctl, unsigned* __restrict__ head) {
+  constexpr int RB = Marcher<T, R, MFIX>::RB;
+  __shared__ T s_bfp[RB][9][LROW];
+  for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
+  __syncthreads();
+  // descriptors, counters and the work list are not written while the kernel
+  // runs: uniform reads through the scalar cache
+  const cptr<BatchCtl> c = as_const(ctl);
+  const cptr<BatchItem> items = as_const(c->items);
+  const unsigned nitems = (unsigned)c->nitems;
+  const cptr<SlotStep> st = as_const(steps);
+  for (;;) {
+    unsigned it = 0;
+    if (threadIdx.x == 0) it = atomicAdd(head, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= nitems) break;
+    const BatchItem w = load_const(items + it);
+    const int64_t n = st[w.slot].n;
+    if (n >= st[w.slot].target) continue;
+    const cptr<GridDesc<T>> d = as_const(desc) + w.slot;
+    const StepArgs<T> a = load_const(as_const(&d->a));
+    const int strip = w.tile % a.nstrips;
+    const int seg = w.tile / a.nstrips;
+    const int b = (int)(n & 1);
+    const double pend = MFIX ? d->hdr->pending : 0.0;
+    march_tile<T, R, MFIX>(a, n, d->buf[b], d->buf[b ^ 1], d->cf, d->tabx, d->taby, d->part,
+                           pend, strip, seg, s_bfp);
+    // the next item's ring starts from its own rows; order this tile's LDS
+    // reads before them
+    wave_sync();
+  }
+}
+
+// After each batch step: per active slot, the fused mass correction (MFIX)
+// and n += 1; block 0 rewinds the work queue for the next step.
+template <typename T, bool MFIX>
+__global__ __launch_bounds__(MASS_THREADS) void batch_finish_kernel(
+    const GridDesc<T>* __restrict__ desc, SlotStep* __restrict__ steps,
+    unsigned* __restrict__ head) {
+  const int slot = blockIdx.x;
+  if (slot == 0 && threadIdx.x == 0) *head = 0u;
+  const int64_t n = steps[slot].n;
+  if (n >= steps[slot].target) return;
+  if (MFIX) mass_fix_block(desc[slot].part, desc[slot].ngroups, desc[slot].hdr, desc[slot].ncells);
+  if (threadIdx.x == 0) steps[slot].n = n + 1;
 }
 
 // ------------------------------------------------------------------ init
@@ -423,39 +656,40 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ phi
+// f~_i of the state: the stored value plus the pending correction w_i delta,
+// rounded as the step kernel rounds it when it loads the value
+template <typename T>
+__device__ __forceinline__ T stored_f(T v, int i, double pend) {
+  return pend != 0.0 ? v + T(wq(i) * pend) : v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void phi_kernel(const T* __restrict__ buf, Tiling tl,
+                                                  const StateHeader* __restrict__ hdr,
                                                   T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= tl.nx || y >= tl.ny) return;
   const int64_t o = tl.idx(0, y, x);
-  T s = buf[o];
+  const double pend = hdr->pending;
+  T s = stored_f(buf[o], 0, pend);
 #pragma unroll
-  for (int i = 1; i < 9; i++) s += buf[o + i * OWN];
+  for (int i = 1; i < 9; i++) s += stored_f(buf[o + i * OWN], i, pend);
   out[(int64_t)y * tl.nx + x] = s;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void export_kernel(const T* __restrict__ buf, Tiling tl,
+                                                     const StateHeader* __restrict__ hdr,
                                                      T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   const int i = blockIdx.z;
   if (x >= tl.nx || y >= tl.ny) return;
-  out[((int64_t)i * tl.ny + y) * tl.nx + x] = buf[tl.idx(i, y, x)];
+  out[((int64_t)i * tl.ny + y) * tl.nx + x] = stored_f(buf[tl.idx(i, y, x)], i, hdr->pending);
 }
 
 // ------------------------------------------------------------------ mass
-// Neumaier pair (sum, compensation)
-__device__ __forceinline__ void neu_add(double& s, double& c, double v) {
-  double t = s + v;
-  if (fabs(s) >= fabs(v))
-    c += (s - t) + v;
-  else
-    c += (v - t) + s;
-  s = t;
-}
 
 // block partials of sum(phi) over a fixed cell partition: partial b covers the
 // cells b, b + MASS_BLOCKS*MASS_THREADS, ... of thread order; every reduction
@@ -463,10 +697,12 @@ __device__ __forceinline__ void neu_add(double& s, double& c, double v) {
 // the 9 distributions in strip chunks; otherwise a dense [ny][nx] FP64 field.
 template <typename T, bool STATE>
 __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
-    const T* __restrict__ f, Tiling tl, double* __restrict__ part) {
+    const T* __restrict__ f, Tiling tl, const StateHeader* __restrict__ hdr,
+    double* __restrict__ part) {
   __shared__ double ss[MASS_THREADS], sc[MASS_THREADS];
   const int nx = tl.nx;
   const int64_t N = (int64_t)nx * tl.ny;
+  const double pend = STATE ? hdr->pending : 0.0;
   double s = 0.0, c = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * MASS_THREADS + threadIdx.x; j < N;
        j += (int64_t)MASS_BLOCKS * MASS_THREADS) {
@@ -474,9 +710,9 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
     double v;
     if (STATE) {
       const int64_t o = tl.idx(0, y, x);
-      v = (double)f[o];
+      v = (double)stored_f(f[o], 0, pend);
 #pragma unroll
-      for (int i = 1; i < 9; i++) v += (double)f[o + i * OWN];
+      for (int i = 1; i < 9; i++) v += (double)stored_f(f[o + i * OWN], i, pend);
     } else {
       v = (double)f[j];
     }
@@ -500,7 +736,7 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
   }
 }
 
-__global__ __launch_bounds__(64) void mass_final_kernel(const double* __restrict__ part,
+static __global__ __launch_bounds__(64) void mass_final_kernel(const double* __restrict__ part,
                                                         double* __restrict__ out,
                                                         double* __restrict__ out2) {
   if (threadIdx.x != 0) return;
