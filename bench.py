@@ -6,8 +6,12 @@ conservative Allen-Cahn equation on a 4096 x 4096 periodic grid, upwind-3
 tanh circles (R 20-200 cells, seed 0) in rigid rotation (corner speed 0.05).
 State is resident in HBM before the timed region; the timed region is exactly
 --steps calls of the step (one fused kernel each).  FP64 is the headline line;
-the FP32 form (with its FP64 mass correction every --mass-every steps) is
-reported in the same line.
+the FP32 form (FP32 storage, FP64 mass sums and the fused mass correction on
+every step) is reported in the same line, and so are the batched form (256
+uneven grids, 32-512 per side, one persistent kernel, hipGraph replays of 50
+steps, autotuned tile height, against one launch per grid and step) and the
+serving form (a scaled request stream served by continuous batching, against
+one-at-a-time execution).
 
 MLUPS = nx * ny * steps / time / 1e6.  Algorithmic traffic per lattice update:
 f~^n in and f~^{n+1} out (9 + 9 words), phi^{n-1} in and phi^n out (2 words):
@@ -32,21 +36,22 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--mass-every", type=int, default=10)
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one precision only (profiling runs)")
     return ap.parse_args()
 
 
-def time_steps(solver, steps, warmup, mass_every=0):
+def time_steps(solver, steps, warmup):
     """Warm up, then time exactly `steps` steps with HIP events on the stream
-    the kernels run on; returns (seconds, mean kernel-region ms per step)."""
+    the kernels run on; returns (seconds, ms of the timed region)."""
     import torch
     for k in range(warmup):
         solver.step(1)
-        if mass_every and (k + 1) % mass_every == 0:
-            solver.mass_correct()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
@@ -55,8 +60,6 @@ def time_steps(solver, steps, warmup, mass_every=0):
     start.record(stream)
     for k in range(steps):
         solver.step(1)
-        if mass_every and (k + 1) % mass_every == 0:
-            solver.mass_correct()
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -121,6 +124,102 @@ def profile_traffic(kernel_prefix: str, precision: str):
         return None
 
 
+def bench_batched(steps):
+    """C4: 256 independent grids, FP32 + fused mass correction, upwind-3.
+    Batched: one persistent kernel per step over all grids, hipGraph replays
+    of 50 steps, tile height from the autotuner.  Plain: each grid alone, one
+    step kernel (+ its mass-correction kernel) per launch."""
+    import torch
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd import inputs as I
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+    grids = I.batch_grids(256, seed=0)
+    cells = sum(g["nx"] * g["ny"] for g in grids)
+
+    def make():
+        out = []
+        for g in grids:
+            out.append(Solver(g["nx"], g["ny"], g["mobility"], g["width"], g["cfl"],
+                              recon=g["recon"], precision=C.F32, vel_kind=g["vel_kind"],
+                              vel_param=g["vel_param"], flags=C.FLAG_MASS_FIX)
+                       .init(I.batch_phi0(g)))
+        return out
+
+    sol = make()
+    b = Batch(len(grids), C.F32, C.UPWIND3, C.FLAG_MASS_FIX)
+    for k, s in enumerate(sol):
+        b.set(k, s, steps + 10)
+    b.commit()
+    b.step(2, graph_steps=0)
+    rows = b.tune(reps=3)
+    b.step(8, graph_steps=0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps, graph_steps=50)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) * 1e-3
+    st = b.sync()
+    assert all(int(x) == steps + 10 for x in st[:len(grids), 0])
+    del b, sol
+    sol = make()
+    for s in sol:
+        s.step(2)
+    torch.cuda.synchronize()
+    e0.record()
+    for s in sol:
+        s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) * 1e-3
+    del sol
+    torch.cuda.empty_cache()
+    lus = cells * steps
+    return {"workload": f"256 periodic grids, sides log-uniform 32-512 (seed 0), {cells} "
+                        f"cells in all, upwind-3, FP32 + fused mass correction, {steps} "
+                        "steps each",
+            "value": round(lus / t_batch / 1e6, 1), "unit": "MLUPS",
+            "plain_one_grid_per_launch": round(lus / t_plain / 1e6, 1),
+            "speedup": round(t_plain / t_batch, 2), "tile_rows": rows,
+            "graph_steps": 50, "seconds": round(t_batch, 4),
+            "plain_seconds": round(t_plain, 4)}
+
+
+def bench_serving(count):
+    """C5, scaled to a bench run: Poisson arrivals at 200/s of square solves,
+    sides log-uniform 64-1024, 500-5000 steps, FP32; continuous batching vs
+    one-at-a-time in arrival order on the same trace, then the batched server
+    again at ~70 % of its measured capacity."""
+    import numpy as np
+    from paper_2007_07760_amd import inputs as I
+    from paper_2007_07760_amd import serve as S
+    trace = I.serve_trace(count=count, rate=200.0, nmin=64, nmax=1024, smin=500,
+                          smax=5000, seed=0)
+    srv = S.Server(slots=64, budget_bytes=48 << 30, graph_steps=16)
+    sample = [r["id"] for r in trace[:: max(1, len(trace) // 8)]][:8]
+    res = srv.run(trace, keep_phi=sample)
+    sat = S.summary(res)
+    fifo = S.summary(S.run_fifo(trace))
+    same = all(np.array_equal(r.phi, S.run_alone(trace[r.id])) for r in res
+               if r.phi is not None)
+    lu_req = sat["lattice_updates"] / len(trace)
+    rate = 0.7 * sat["mlups"] * 1e6 / lu_req
+    trace2 = I.serve_trace(count=count, rate=rate, nmin=64, nmax=1024, smin=500,
+                           smax=5000, seed=1)
+    unsat = S.summary(srv.run(trace2))
+    del srv
+
+    def r4(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"workload": f"{count} requests, Poisson 200/s, N 64-1024 log-uniform, "
+                        "500-5000 steps, single vortex / rotation, upwind-3, FP32",
+            "batched": r4(sat), "one_at_a_time": r4(fifo),
+            "mix_equals_alone_sampled": bool(same), "samples": len(sample),
+            "unsaturated": dict(r4(unsat), rate_per_s=round(rate, 1))}
+
+
 def cpu_baseline(w):
     """The FP64 oracle as it stands, on this host's cores, on a bounded sample of
     the same workload: its first step on the full 4096^2 grid."""
@@ -163,9 +262,9 @@ def main():
             continue
         s = Solver(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                    recon=w["recon"], precision=prec, vel_kind=w["vel_kind"],
-                   vel_param=w["vel_param"], tile_rows=args.tile_rows).init(w["phi0"])
-        me = args.mass_every if prec == C.F32 else 0
-        wall, ev_ms = time_steps(s, args.steps, args.warmup, me)
+                   vel_param=w["vel_param"], tile_rows=args.tile_rows,
+                   flags=C.FLAG_MASS_FIX if prec == C.F32 else 0).init(w["phi0"])
+        wall, ev_ms = time_steps(s, args.steps, args.warmup)
         k_ms = time_kernel_only(s, min(args.steps, 50))
         esize = 8 if prec == C.F64 else 4
         alg_bytes = WORDS_PER_LU * esize * lus
@@ -210,11 +309,15 @@ def main():
         f = results["f32"]
         line["fp32"] = {"value": round(f["mlups"], 1), "unit": "MLUPS",
                         "ms_per_step": round(f["ev_ms"] / args.steps, 4),
-                        "mass_correction_every": args.mass_every,
+                        "mass_correction": "fused, every step",
                         "kernel_ms": round(f["kernel_ms"], 4),
                         "achieved": round(f["achieved"], 1),
                         "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
                         "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4}
+    if not args.no_batch and not args.only:
+        line["batched"] = bench_batched(args.batch_steps)
+    if not args.no_serve and not args.only:
+        line["serving"] = bench_serving(args.serve_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

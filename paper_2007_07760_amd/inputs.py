@@ -130,3 +130,81 @@ def workload(name: str, seed: int = 0) -> dict:
                     phi0=random_circles(n, n, 64, 20.0, 200.0, 4.0, seed),
                     steps=200)
     raise KeyError(name)
+
+
+# ------------------------------------------------------ batched and serving
+def batch_grids(count: int = 256, seed: int = 0, nmin: int = 32, nmax: int = 512) -> list:
+    """Independent periodic grids of uneven size for the batched form: sides
+    log-uniform in [nmin, nmax], 1-4 tanh circles with radii 5-25 % of the
+    shorter side (union by max), and half the grids in uniform flow (random
+    angle, |u| <= 0.05), half in rotation about the grid centre (largest
+    speed, at the corners, <= 0.05); upwind-3, W = 4, M = 0.01, C = 0.5.
+    phi0 is drawn by `batch_phi0(grid)`."""
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(nmin), math.log(nmax)
+    out = []
+    for k in range(count):
+        nx = int(round(math.exp(rng.uniform(lo, hi))))
+        ny = int(round(math.exp(rng.uniform(lo, hi))))
+        m = min(nx, ny)
+        ncirc = int(rng.integers(1, 5))
+        cseed = int(rng.integers(0, 2 ** 31 - 1))
+        if rng.random() < 0.5:
+            ang, sp = rng.uniform(0.0, 2 * math.pi), rng.uniform(0.0, 0.05)
+            kind, prm = VEL_UNIFORM, (sp * math.cos(ang), sp * math.sin(ang))
+        else:
+            umax = rng.uniform(0.0, 0.05)
+            omega = umax / math.hypot(nx / 2, ny / 2)
+            kind, prm = VEL_ROTATION, (omega, nx / 2, ny / 2)
+        out.append(dict(nx=nx, ny=ny, mobility=0.01, width=4.0, cfl=0.5, recon=UPWIND3,
+                        vel_kind=kind, vel_param=prm, circles=ncirc, rmin=0.05 * m,
+                        rmax=0.25 * m, seed=cseed, steps=2000))
+    return out
+
+
+def batch_phi0(g: dict) -> np.ndarray:
+    return random_circles(g["nx"], g["ny"], g["circles"], g["rmin"], g["rmax"],
+                          g["width"], g["seed"])
+
+
+def serve_trace(count: int = 1000, rate: float = 200.0, nmin: int = 64, nmax: int = 4096,
+                smin: int = 500, smax: int = 20000, seed: int = 0) -> list:
+    """Request stream of interface-tracking solves: Poisson arrivals (mean
+    `rate` per second), square grids with sides log-uniform in [nmin, nmax],
+    step counts uniform in [smin, smax].  Half the requests are a single vortex
+    (U0 = 0.05, modulated by cos(pi t / (steps dt)) so that the flow reverses
+    at half time; circle R = 0.15 N at (0.5 N, 0.75 N), not wrapped), half a
+    rigid rotation about the centre with corner speed 0.05 (circle R = 0.15 N
+    at (0.5 N, 0.65 N), periodic); upwind-3, W = 4, M = 0.01, C = 0.5."""
+    rng = np.random.default_rng(seed)
+    lo, hi = math.log(nmin), math.log(nmax)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(math.exp(rng.uniform(lo, hi))))
+        steps = int(rng.integers(smin, smax + 1))
+        cfl = 0.5
+        if rng.random() < 0.5:
+            kind, prm = VEL_SINGLE_VORTEX, (0.05, steps * cfl)
+            circle = (0.5 * n, 0.75 * n, 0.15 * n, False)
+        else:
+            kind, prm = VEL_ROTATION, (0.05 / (math.sqrt(2.0) * n / 2), n / 2, n / 2)
+            circle = (0.5 * n, 0.65 * n, 0.15 * n, True)
+        out.append(dict(id=k, arrival=t, nx=n, ny=n, steps=steps, mobility=0.01, width=4.0,
+                        cfl=cfl, recon=UPWIND3, vel_kind=kind, vel_param=prm, circle=circle))
+    return out
+
+
+def tanh_circle_torch(nx: int, ny: int, cx: float, cy: float, radius: float, width: float,
+                      periodic: bool, device) -> "torch.Tensor":
+    """tanh_circle drawn directly in device memory (FP64), for requests whose
+    phi0 is too large to draw on the host at arrival rate."""
+    import torch
+    x = torch.arange(nx, dtype=torch.float64, device=device) + 0.5 - cx
+    y = torch.arange(ny, dtype=torch.float64, device=device) + 0.5 - cy
+    if periodic:
+        x = x - nx * torch.round(x / nx)
+        y = y - ny * torch.round(y / ny)
+    r = torch.sqrt(y[:, None] ** 2 + x[None, :] ** 2)
+    return 0.5 + 0.5 * torch.tanh(2.0 * (radius - r) / width)

@@ -17,7 +17,7 @@ class Solver:
 
     def __init__(self, nx, ny, mobility, width, cfl, recon=C.UPWIND3,
                  precision=C.F64, vel_kind=C.VEL_UNIFORM, vel_param=(0.0, 0.0),
-                 flags=0, tile_rows=0, device="cuda"):
+                 flags=0, tile_rows=0, device="cuda", state=None):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (no CPU path exists)")
         self.params = C.make_params(nx, ny, mobility, width, cfl, recon, precision,
@@ -27,8 +27,12 @@ class Solver:
         self.dtype = torch.float64 if precision == C.F64 else torch.float32
         self.plan = C.dugks_plan_create(self.params)
         self.device = torch.device(device)
-        self.state = torch.empty(C.dugks_state_bytes(self.plan), dtype=torch.uint8,
-                                 device=self.device)
+        nbytes = C.dugks_state_bytes(self.plan)
+        if state is None:
+            state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif state.numel() < nbytes or state.data_ptr() % 256:
+            raise ValueError("state memory too small or not 256-byte aligned")
+        self.state = state          # uint8 device tensor (possibly a view of a pool)
         self.step_index = 0
         self._scalar = torch.empty(1, dtype=torch.float64, device=self.device)
 
