@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="the batched section alone (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one precision only (profiling runs)")
@@ -256,6 +258,9 @@ def main():
         w = dict(w, nx=n, ny=n, phi0=I.random_circles(n, n, 64, 20.0 * n / 4096,
                                                       200.0 * n / 4096, 4.0, 0))
     lus = w["nx"] * w["ny"]
+    if args.only_batch:
+        print(json.dumps({"batched": bench_batched(args.batch_steps)}), flush=True)
+        return
     results = {}
     for prec_name, prec in (("f64", C.F64), ("f32", C.F32)):
         if args.only and args.only != prec_name:

@@ -239,8 +239,9 @@ int launch_step_t(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
   }
 #undef DUGKS_LAUNCH
   if (MFIX)
-    hipLaunchKernelGGL(mass_fix_kernel, dim3(1), dim3(MASS_THREADS), 0, s, part,
-                       L.tl.nstrips * L.ngroups, hd, (double)P->p.nx * (double)P->p.ny);
+    hipLaunchKernelGGL(mass_fix_strips_kernel, dim3(L.tl.nstrips), dim3(LANES), 0, s,
+                       part, L.ngroups, L.tl.nstrips, at<double>(state, L.off_strips), hd,
+                       (double)P->p.nx * (double)P->p.ny);
   return hip_status(hipGetLastError());
 }
 

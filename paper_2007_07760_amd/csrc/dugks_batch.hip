@@ -83,7 +83,9 @@ GridDesc<T> make_desc(const Slot& s, int rows) {
   d.hdr = at<StateHeader>(s.state, 0);
   d.part = at<double>(s.state, L.off_groups);
   d.ncells = (double)P->p.nx * (double)P->p.ny;
-  d.ngroups = L.tl.nstrips * L.ngroups;
+  d.strip_part = at<double>(s.state, L.off_strips);
+  d.groups_per_strip = L.ngroups;
+  d.nstrips = L.tl.nstrips;
   return d;
 }
 
@@ -187,7 +189,7 @@ int launch_batch_step(dugks_batch* B, hipStream_t s, bool finish) {
   hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
                      static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_ctl, B->d_head);
   if (finish)
-    hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(B->cap), dim3(MASS_THREADS), 0, s,
+    hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(B->cap), dim3(FIX_THREADS), 0, s,
                        static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_head);
   return hip_status(hipGetLastError());
 }

@@ -123,8 +123,9 @@ struct StateHeader {
   double mass_now;     // last measured total
   double pending;      // fused correction: f~_i = stored f~_i + w_i pending
   int32_t nx, ny, precision, recon;
-  double mass_step;    // fused correction: M^n as the last step wrote it
   double sigma;        // fused correction: fraction of delta that survives rounding
+  int32_t fix_count;   // fused correction: strips reduced so far in this step
+  int32_t pad32;
   int64_t pad[24];
 };
 static_assert(sizeof(StateHeader) == 256, "header size");
@@ -135,11 +136,12 @@ constexpr int MASS_THREADS = 256;
 // The fused mass correction sums phi^{n+1} in groups of MASS_GROUP rows of one
 // strip; segments of such plans are whole groups.
 constexpr int MASS_GROUP = 8;
+constexpr int FIX_THREADS = 1024;   // threads of the block that reduces the groups
 
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)
   Tiling tl;
-  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, off_groups, total;
+  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, off_groups, off_strips, total;
   int ngroups;         // row groups per strip
 };
 
@@ -170,6 +172,8 @@ inline Layout make_layout(int nx, int ny, int precision) {
   L.ngroups = (ny + MASS_GROUP - 1) / MASS_GROUP;
   L.off_groups = off;
   off = align_up(off + 2 * (size_t)L.tl.nstrips * L.ngroups * sizeof(double), 256);
+  L.off_strips = off;
+  off = align_up(off + 2 * (size_t)L.tl.nstrips * sizeof(double), 256);
   L.total = off;
   return L;
 }

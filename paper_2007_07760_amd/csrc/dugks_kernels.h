@@ -141,8 +141,8 @@ struct Marcher {
   // mass correction (MFIX): the stored f~_i lack w_i delta, delta being the
   // per-cell correction set after the previous step; cw0..2 = w_i delta per
   // weight class.  Per row group the lane sums the phi it writes (macc) and
-  // the corrected f~ it read (oacc, which tells how much of delta survived
-  // the rounding to T); the group totals go to part_row[2 group + 0 / 1].
+  // how much of the correction survived the rounding of f~_i + w_i delta to T
+  // (oacc); the group totals go to part_row[2 group + 0 / 1].
   T cw0, cw1, cw2;
   double macc, oacc;
   double* part_row;
@@ -313,7 +313,8 @@ struct Marcher {
     // 21); f~ of row k is read again here (cache hit) rather than held in
     // registers across the two rows of the pipeline
     const T third = T(1) / T(3);
-    double cs = 0.0, co = 0.0;
+    double cs = 0.0;
+    T ce = T(0);
     if (owned) {
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
@@ -327,7 +328,7 @@ struct Marcher {
         __builtin_nontemporal_store(v, o + i * OWN);
         if (MFIX) {
           cs += (double)v;
-          co += (double)fo;
+          ce += fo - p[i * OWN];   // the rounded increment: exact in T
         }
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
@@ -337,7 +338,7 @@ struct Marcher {
       // two segments (segments are whole groups), so its sum -- lanes in a
       // fixed butterfly after rows in order -- does not depend on the tiling
       macc += cs;
-      oacc += co;
+      oacc += (double)ce;
       if ((k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1) {
         double v = macc, w = oacc;
 #pragma unroll
@@ -473,55 +474,109 @@ __device__ __forceinline__ void neu_add(double& s, double& c, double v) {
 }
 
 // After a step with the fused correction.  The partials hold, per row group,
-// the new total (M^{n+1}) and the total of the corrected f~^n the step read
-// (the mass the state really had after the last correction).  The part of the
-// last correction that survived the rounding of f~_i + w_i delta to T is
-// sigma = (that total - M^n) / (N delta); the next correction is
-// delta = (M0 - M^{n+1}) / (N sigma), so that what survives of it restores M0.
-// sigma keeps its last value while the correction is too small to measure.
-__device__ __forceinline__ void mass_fix_block(const double* __restrict__ part, int ngroups,
-                                               StateHeader* __restrict__ hdr, double ncells) {
-  __shared__ double ss[2][MASS_THREADS], sc[2][MASS_THREADS];
-  double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
-  for (int j = threadIdx.x; j < ngroups; j += MASS_THREADS) {
-    neu_add(s[0], c[0], part[2 * j]);
-    neu_add(s[1], c[1], part[2 * j + 1]);
+// the new total (M^{n+1}) and the part of the last correction that survived
+// the rounding of f~_i + w_i delta to T, which is sigma N delta.  The next
+// correction is delta = (M0 - M^{n+1}) / (N sigma), so that what survives of
+// it restores M0.  sigma keeps its last value while the correction is too
+// small to measure.
+__device__ __forceinline__ void mass_fix_set(StateHeader* __restrict__ hdr, double m_new,
+                                             double survived, double ncells) {
+  const double applied = hdr->pending * ncells;
+  double sigma = hdr->sigma > 0.0 ? hdr->sigma : 1.0;
+  if (fabs(applied) > 1e-13 * fabs(hdr->mass0)) {
+    const double sv = survived / applied;
+    if (sv >= 0.0625 && sv <= 1.5) sigma = sv;
   }
-  for (int q = 0; q < 2; q++) {
-    ss[q][threadIdx.x] = s[q];
-    sc[q][threadIdx.x] = c[q];
-  }
-  __syncthreads();
-  for (int w = MASS_THREADS / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      for (int q = 0; q < 2; q++) {
-        double a = ss[q][threadIdx.x], ac = sc[q][threadIdx.x] + sc[q][threadIdx.x + w];
-        neu_add(a, ac, ss[q][threadIdx.x + w]);
-        ss[q][threadIdx.x] = a;
-        sc[q][threadIdx.x] = ac;
-      }
+  hdr->sigma = sigma;
+  hdr->mass_now = m_new;
+  hdr->pending = (hdr->mass0 - m_new) / (ncells * sigma);
+}
+
+// Fixed-order (Neumaier) sum of n pairs (v[2j], v[2j+1]) by one wavefront:
+// lane l takes the pairs l, l + 64, ... (U loads in flight), then the lanes
+// are folded in halves.  Lane 0 receives the two totals.  The order depends
+// on n only, so any wavefront of any kernel computes the same bits.
+__device__ __forceinline__ void wave_pair_sum(const double* __restrict__ v, int n, double& t0,
+                                              double& t1) {
+  constexpr int U = 8;
+  const int lane = threadIdx.x & (LANES - 1);
+  double s0 = 0.0, c0 = 0.0, s1 = 0.0, c1 = 0.0;
+  for (int j0 = lane; j0 < n; j0 += U * LANES) {
+    double w[U][2];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int j = j0 + u * LANES;
+      w[u][0] = j < n ? v[2 * j] : 0.0;
+      w[u][1] = j < n ? v[2 * j + 1] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      neu_add(s0, c0, w[u][0]);
+      neu_add(s1, c1, w[u][1]);
+    }
   }
+#pragma unroll
+  for (int off = LANES / 2; off > 0; off >>= 1) {
+    const double os0 = __shfl_down(s0, off), oc0 = __shfl_down(c0, off);
+    const double os1 = __shfl_down(s1, off), oc1 = __shfl_down(c1, off);
+    if (lane < off) {
+      c0 += oc0;
+      neu_add(s0, c0, os0);
+      c1 += oc1;
+      neu_add(s1, c1, os1);
+    }
+  }
+  t0 = s0 + c0;
+  t1 = s1 + c1;
+}
+
+// One-grid reduction in one launch: wavefront b sums the groups of strip b
+// into strip_part[b]; the last one to finish (counted in the header, with
+// device-scope release / acquire around the count) sums the strips in order
+// and sets the correction.
+static __global__ __launch_bounds__(LANES) void mass_fix_strips_kernel(
+    const double* __restrict__ part, int groups_per_strip, int nstrips,
+    double* __restrict__ strip_part, StateHeader* __restrict__ hdr, double ncells) {
+  double a, b;
+  wave_pair_sum(part + 2 * (int64_t)blockIdx.x * groups_per_strip, groups_per_strip, a, b);
+  int last = 0;
   if (threadIdx.x == 0) {
-    const double m_new = ss[0][0] + sc[0][0];
-    const double m_read = ss[1][0] + sc[1][0];
-    const double applied = hdr->pending * ncells;
-    double sigma = hdr->sigma > 0.0 ? hdr->sigma : 1.0;
-    if (fabs(applied) > 1e-13 * fabs(hdr->mass0)) {
-      const double sv = (m_read - hdr->mass_step) / applied;
-      if (sv >= 0.0625 && sv <= 1.5) sigma = sv;
-    }
-    hdr->sigma = sigma;
-    hdr->mass_step = m_new;
-    hdr->mass_now = m_new;
-    hdr->pending = (hdr->mass0 - m_new) / (ncells * sigma);
+    strip_part[2 * blockIdx.x] = a;
+    strip_part[2 * blockIdx.x + 1] = b;
+    __threadfence();
+    last = atomicAdd(&hdr->fix_count, 1) == nstrips - 1;
+  }
+  last = __shfl(last, 0);
+  if (!last) return;
+  __threadfence();
+  wave_pair_sum(strip_part, nstrips, a, b);
+  if (threadIdx.x == 0) {
+    mass_fix_set(hdr, a, b, ncells);
+    hdr->fix_count = 0;
   }
 }
 
-static __global__ __launch_bounds__(MASS_THREADS) void mass_fix_kernel(
-    const double* __restrict__ part, int ngroups, StateHeader* __restrict__ hdr, double ncells) {
-  mass_fix_block(part, ngroups, hdr, ncells);
+// The same sums by one block for one grid of a batch: its wavefronts take
+// the strips in turn, wavefront 0 then sums the strips.
+__device__ __forceinline__ void mass_fix_block(const double* __restrict__ part,
+                                               int groups_per_strip, int nstrips,
+                                               double* __restrict__ strip_part,
+                                               StateHeader* __restrict__ hdr, double ncells) {
+  const int wave = threadIdx.x / LANES, nwaves = blockDim.x / LANES;
+  for (int st = wave; st < nstrips; st += nwaves) {
+    double a, b;
+    wave_pair_sum(part + 2 * (int64_t)st * groups_per_strip, groups_per_strip, a, b);
+    if ((threadIdx.x & (LANES - 1)) == 0) {
+      strip_part[2 * st] = a;
+      strip_part[2 * st + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double a, b;
+    wave_pair_sum(strip_part, nstrips, a, b);
+    if (threadIdx.x == 0) mass_fix_set(hdr, a, b, ncells);
+  }
 }
 
 // ------------------------------------------------------------------ batch
@@ -541,9 +596,10 @@ struct GridDesc {
   const T* taby;
   StateHeader* hdr;
   double* part;       // row-group partials of the fused mass correction
+  double* strip_part; // their per-strip totals
   double ncells;
-  int ngroups;        // row groups over all strips (two partials each)
-  int pad;
+  int groups_per_strip;
+  int nstrips;
 };
 
 struct SlotStep {
@@ -600,14 +656,18 @@ __global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void batch_step_ke
 // After each batch step: per active slot, the fused mass correction (MFIX)
 // and n += 1; block 0 rewinds the work queue for the next step.
 template <typename T, bool MFIX>
-__global__ __launch_bounds__(MASS_THREADS) void batch_finish_kernel(
+__global__ __launch_bounds__(FIX_THREADS) void batch_finish_kernel(
     const GridDesc<T>* __restrict__ desc, SlotStep* __restrict__ steps,
     unsigned* __restrict__ head) {
   const int slot = blockIdx.x;
   if (slot == 0 && threadIdx.x == 0) *head = 0u;
   const int64_t n = steps[slot].n;
   if (n >= steps[slot].target) return;
-  if (MFIX) mass_fix_block(desc[slot].part, desc[slot].ngroups, desc[slot].hdr, desc[slot].ncells);
+  if (MFIX) {
+    const GridDesc<T>& d = desc[slot];
+    mass_fix_block(d.part, d.groups_per_strip, d.nstrips, d.strip_part, d.hdr, d.ncells);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) steps[slot].n = n + 1;
 }
 
