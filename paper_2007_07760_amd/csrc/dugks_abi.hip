@@ -196,14 +196,14 @@ int validate(const dugks_params* p) {
 }
 
 // Default rows per wavefront.  Resident wavefronts of the step kernel on one
-// MI355X (256 CUs; per CU 8 in FP64 and 16 in FP32, limited by the LDS ring and
-// registers, 6/12 for the 5-row ring of central-4).  A wavefront marches
+// MI355X: 256 CUs, each 4 SIMDs x step_waves (the register budget the kernel
+// variant is built for; the LDS ring fits that many).  A wavefront marches
 // seg + 4 rows of work; the launch runs in ceil(tiles / resident) rounds, so
 // pick the segment that minimises rounds * (seg + 4): whole rounds, little
 // halo.  Segments are whole mass groups (multiples of MASS_GROUP rows).
 int default_tile_rows(const dugks_params& p, int nstrips) {
-  const bool c4 = p.recon == DUGKS_CENTRAL4;
-  const int per_cu = p.precision == DUGKS_F64 ? (c4 ? 6 : 8) : (c4 ? 12 : 16);
+  const int per_cu = 4 * step_waves(p.precision == DUGKS_F64 ? 8 : 4, p.recon,
+                                    (p.flags & DUGKS_FLAG_MASS_FIX) != 0);
   const long resident = 256L * per_cu;
   int best = 64;
   long best_cost = -1;

@@ -97,6 +97,15 @@ constexpr int OWN = LANES - 2 * HALO;
 constexpr int LPAD = 2;                 // LDS row padding each side
 constexpr int LROW = LANES + 2 * LPAD;  // LDS row length (elements)
 
+
+// Wavefronts per SIMD the step kernels are built for (the register budget of
+// each variant: 512 / waves VGPRs), and so resident per CU (x 4 SIMDs).  The
+// FP32 variants with the fused mass correction or the 5-row ring of central-4
+// need more than 128 registers: 3.
+__host__ __device__ constexpr int step_waves(int esize, int recon, bool mfix) {
+  return esize == 8 ? 2 : ((recon == DUGKS_CENTRAL4 || mfix) ? 3 : 4);
+}
+
 // ------------------------------------------------------------- state layout
 // The distributions live in strip chunks: the grid is cut into strips of OWN
 // columns (the columns one wavefront owns), and row y of strip s holds the 9

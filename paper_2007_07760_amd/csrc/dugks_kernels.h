@@ -32,6 +32,7 @@ struct StepArgs {
   int seg_rows, nstrips, nsegs, nlogical;
   int ngroups;           // row groups of MASS_GROUP rows (mass partials)
   T cB2;                 // fbar+ = f~ + cB2 (feq + tau S - f~)
+  T kap;                 // f~+ = fbar+ + kap (feq + tau S - fbar+)
   T pscale;              // beta / alpha (the stencil table carries dt*alpha)
   T gdt;                 // dt * gamma / 2 (face S is the mean of two cells)
   T dt, tau, kth;        // kth = 4/W (0: theta off)
@@ -114,6 +115,23 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// X_i = (feq + tau S)_i = w_i (phi + e_i . m),  m = phi u / RT + tau s,
+// per weight class and direction pair, the rest weight taking what the others
+// leave so that sum_i X_i = phi with no systematic rounding bias
+template <typename T>
+__device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
+  const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+  const T P1 = w1 * pC, P2 = w2 * pC;
+  const T X1 = w1 * mx, Y1 = w1 * my;
+  const T X2 = w2 * mx, Y2 = w2 * my;
+  const T dpp = X2 + Y2, dmp = Y2 - X2;
+  x[0] = fma(T(-4), P1 + P2, pC);
+  x[1] = P1 + X1; x[5] = P1 - X1;
+  x[3] = P1 + Y1; x[7] = P1 - Y1;
+  x[2] = P2 + dpp; x[6] = P2 - dpp;
+  x[4] = P2 + dmp; x[8] = P2 - dmp;
+}
+
 template <typename T, int R, bool MFIX>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
@@ -136,15 +154,17 @@ struct Marcher {
   T D0, D1, D2;             // phi(x+1) - phi(x-1) of rows r-1 .. r+1
   T A0, A1, A2;             // phi(x-1) + 4 phi(x) + phi(x+1) of rows r-1 .. r+1
   T sx0, sy0, sx1, sy1, sx2, sy2;  // s = theta n + J/RT of rows r-2 .. r
+  T cp0, cp1, cp2, cx0, cx1, cx2, cy0, cy1, cy2;  // phi, m of rows r-2 .. r
   T fS[9];                  // dt*alpha*fbar of the face below (north face of k-1)
   T PS, QSx, QSy;           // its collision part, see face_stage
   // mass correction (MFIX): the stored f~_i lack w_i delta, delta being the
   // per-cell correction set after the previous step; cw0..2 = w_i delta per
   // weight class.  Per row group the lane sums the phi it writes (macc) and
   // how much of the correction survived the rounding of f~_i + w_i delta to T
-  // (oacc); the group totals go to part_row[2 group + 0 / 1].
+  // as its own rows are loaded (oac0 / oac1 by group parity: loads run at most
+  // one group ahead of the faces); the group totals go to part_row[2 g + 0/1].
   T cw0, cw1, cw2;
-  double macc, oacc;
+  double macc, oac0, oac1;
   double* part_row;
 
   __device__ __forceinline__ T cw(int i) const { return i == 0 ? cw0 : ((i & 1) ? cw1 : cw2); }
@@ -157,11 +177,22 @@ struct Marcher {
     return src + (int64_t)rr * a.CH + loff;
   }
 
-  __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) const {
+  __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) {
     const T* p = row_src(wrapi(row, a.ny));
+    T ce = T(0);
 #pragma unroll
-    for (int i = 0; i < 9; i++) d.f[i] = MFIX ? p[i * OWN] + cw(i) : p[i * OWN];
+    for (int i = 0; i < 9; i++) {
+      const T raw = p[i * OWN];
+      d.f[i] = MFIX ? raw + cw(i) : raw;
+      if (MFIX) ce += d.f[i] - raw;   // the rounded increment: exact in T
+    }
     d.hp = p[9 * OWN];
+    if (MFIX && owned && row >= y0 && row < y1) {
+      if ((row / MASS_GROUP) & 1)
+        oac1 += (double)ce;
+      else
+        oac0 += (double)ce;
+    }
   }
 
   // phi = sum_i f~_i (Eq. 30, pairwise) of a new row and its horizontal
@@ -195,22 +226,13 @@ struct Marcher {
     const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
     const T sy = fma(th, gy, T(3) * (Vc * dj));
     sx0 = sx1; sy0 = sy1; sx1 = sx2; sy1 = sy2; sx2 = sx; sy2 = sy;
-    // X_i = (feq + tau S)_i = w_i (phi + e_i . m),  m = phi u / RT + tau s,
-    // per weight class and direction pair, the rest weight taking what the
-    // others leave so that sum_i X_i = phi with no systematic rounding bias
     const T mx = fma(a.tau, sx, T(3) * pC * (gN * Uc));
     const T my = fma(a.tau, sy, T(3) * pC * (gN * Vc));
-    const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
-    const T P1 = w1 * pC, P2 = w2 * pC;
-    const T X1 = w1 * mx, Y1 = w1 * my;
-    const T X2 = w2 * mx, Y2 = w2 * my;
-    const T dpp = X2 + Y2, dmp = Y2 - X2;
+    cp0 = cp1; cp1 = cp2; cp2 = pC;
+    cx0 = cx1; cx1 = cx2; cx2 = mx;
+    cy0 = cy1; cy1 = cy2; cy2 = my;
     T x[9];
-    x[0] = fma(T(-4), P1 + P2, pC);
-    x[1] = P1 + X1; x[5] = P1 - X1;
-    x[3] = P1 + Y1; x[7] = P1 - Y1;
-    x[2] = P2 + dpp; x[6] = P2 - dpp;
-    x[4] = P2 + dmp; x[8] = P2 - dmp;
+    collision_target(pC, mx, my, x);
     // fbar+ in increment form: its moments follow those of X exactly
     T* bf = &bfp[slotB(r)][0][0];
 #pragma unroll
@@ -309,27 +331,23 @@ struct Marcher {
       out[6] += (a2 - ax2) - ay2;
       out[4] += (a2 - ax2) + ay2;
     }
-    // f~+ = fbar+ + (fbar+ - f~) / 3, then f~^{n+1} = f~+ + dt L (Eqs. 9, 23,
-    // 21); f~ of row k is read again here (cache hit) rather than held in
-    // registers across the two rows of the pipeline
-    const T third = T(1) / T(3);
+    // f~+ and fbar+ both relax f~ towards X = feq + tau S (Eqs. 9, 23), so
+    // f~+ = fbar+ + kap (X - fbar+): X of row k is rebuilt from its phi and m
+    // (held since its cell stage) instead of reading f~ of the row again.
+    // Then f~^{n+1} = f~+ + dt L (Eq. 21).
     double cs = 0.0;
-    T ce = T(0);
     if (owned) {
+      T x[9];
+      collision_target(cp0, cx0, cy0, x);
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
-      const T* p = row_src(kk);
 #pragma unroll
       for (int i = 0; i < 9; i++) {
         const T bp = bfp[slotB(k)][i][L];
-        const T fo = MFIX ? p[i * OWN] + cw(i) : p[i * OWN];
-        const T tfp = fma(third, bp - fo, bp);
+        const T tfp = fma(a.kap, x[i] - bp, bp);
         const T v = tfp + out[i];
         __builtin_nontemporal_store(v, o + i * OWN);
-        if (MFIX) {
-          cs += (double)v;
-          ce += fo - p[i * OWN];   // the rounded increment: exact in T
-        }
+        if (MFIX) cs += (double)v;
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
     }
@@ -338,9 +356,9 @@ struct Marcher {
       // two segments (segments are whole groups), so its sum -- lanes in a
       // fixed butterfly after rows in order -- does not depend on the tiling
       macc += cs;
-      oacc += (double)ce;
       if ((k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1) {
-        double v = macc, w = oacc;
+        const bool odd = (k / MASS_GROUP) & 1;
+        double v = macc, w = odd ? oac1 : oac0;
 #pragma unroll
         for (int m = 1; m < LANES; m <<= 1) {
           v += __shfl_xor(v, m);
@@ -351,7 +369,10 @@ struct Marcher {
           part_row[2 * (k / MASS_GROUP) + 1] = w;
         }
         macc = 0.0;
-        oacc = 0.0;
+        if (odd)
+          oac1 = 0.0;
+        else
+          oac0 = 0.0;
       }
     }
   }
@@ -370,7 +391,8 @@ struct Marcher {
 
   __device__ void run() {
     RowRegs<T> B, C;
-    macc = oacc = 0.0;
+    macc = oac0 = oac1 = 0.0;
+    cp0 = cp1 = cp2 = cx0 = cx1 = cx2 = cy0 = cy1 = cy2 = T(0);
     ph0 = ph1 = ph2 = ph3 = T(0);
     D0 = D1 = D2 = A0 = A1 = A2 = T(0);
     sx0 = sy0 = sx1 = sy1 = sx2 = sy2 = T(0);
@@ -441,7 +463,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
 }
 
 template <typename T, int R, bool MFIX>
-__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void step_kernel(
+__global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void step_kernel(
     StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
     const T* __restrict__ cf, const T* __restrict__ tabx, const T* __restrict__ taby,
     double* __restrict__ part, const StateHeader* __restrict__ hdr) {
@@ -618,7 +640,7 @@ struct BatchCtl {
 };
 
 template <typename T, int R, bool MFIX>
-__global__ __launch_bounds__(LANES, (sizeof(T) == 8 ? 2 : 3)) void batch_step_kernel(
+__global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_step_kernel(
     const GridDesc<T>* __restrict__ desc, const SlotStep* __restrict__ steps,
     const BatchCtl* __restrict__ ctl, unsigned* __restrict__ head) {
   constexpr int RB = Marcher<T, R, MFIX>::RB;

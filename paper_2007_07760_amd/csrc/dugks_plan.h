@@ -68,6 +68,7 @@ inline StepArgs<T> step_args(const dugks_plan* P) {
   a.nlogical = P->nstrips * P->nsegs;
   a.ngroups = L.ngroups;
   a.cB2 = T(P->cB2);
+  a.kap = T(P->cB2 / (3.0 * (1.0 - P->cB2)));
   a.pscale = T(P->beta / P->alpha);
   a.gdt = T(0.5 * P->dt * P->gamma);
   a.dt = T(P->dt);
