@@ -88,11 +88,14 @@ typedef enum {
 #define DUGKS_FLAG_DTPHIU_ZERO 1u /* drop d(phi u)/dt from the source (test hook) */
 /* Fused mass correction (meant for FP32 plans): every step also sums
  * phi^{n+1} in FP64 (per 8-row group of each strip, then a fixed-order
- * Neumaier reduction) and records delta = (M0 - M^{n+1}) / (nx ny); the next
- * step adds w_i delta to each f~_i as it loads it.  dugks_phi,
- * dugks_distributions and dugks_mass include the pending delta.  Segments of
- * such plans are whole 8-row groups (tile_rows is rounded up), so results
- * stay independent of the tiling. */
+ * Neumaier reduction) and counts the cells whose new f~_0 is below 1e-3 (the
+ * phase with phi near 0, where a small correction is not lost to rounding).
+ * It records delta = (M0 - M^{n+1}) / count (or / (nx ny), and every cell,
+ * when fewer than 1 % of the cells qualify); the next step adds w_i delta to
+ * each f~_i of those cells as it loads it.  dugks_phi, dugks_distributions
+ * and dugks_mass include the pending correction.  Segments of such plans are
+ * whole 8-row groups (tile_rows is rounded up), so results stay independent
+ * of the tiling. */
 #define DUGKS_FLAG_MASS_FIX 2u
 
 typedef struct {

@@ -263,7 +263,7 @@ int stage_head(const dugks_plan* P) {
   hd->ny = P->p.ny;
   hd->precision = P->p.precision;
   hd->recon = P->p.recon;
-  hd->sigma = 1.0;
+  hd->fit_max = INFINITY;
   // the device table carries dt * alpha (Eq. 27) times the stencil
   T* cf = at<T>(h, L.off_coef);
   for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->alpha * P->compact[k]);

@@ -132,7 +132,7 @@ struct StateHeader {
   double mass_now;     // last measured total
   double pending;      // fused correction: f~_i = stored f~_i + w_i pending
   int32_t nx, ny, precision, recon;
-  double sigma;        // fused correction: fraction of delta that survives rounding
+  double fit_max;      // fused correction: cells with stored f~_0 below it take it
   int32_t fix_count;   // fused correction: strips reduced so far in this step
   int32_t pad32;
   int64_t pad[24];
@@ -145,6 +145,9 @@ constexpr int MASS_THREADS = 256;
 // The fused mass correction sums phi^{n+1} in groups of MASS_GROUP rows of one
 // strip; segments of such plans are whole groups.
 constexpr int MASS_GROUP = 8;
+// the fused correction goes to the cells with f~_0 below this (phi below
+// ~2e-3), where it is far above half an ulp of every f~_i
+constexpr double MASS_FIT_MAX = 1e-3;
 constexpr int FIX_THREADS = 1024;   // threads of the block that reduces the groups
 
 struct Layout {

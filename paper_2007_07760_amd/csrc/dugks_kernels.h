@@ -157,14 +157,14 @@ struct Marcher {
   T cp0, cp1, cp2, cx0, cx1, cx2, cy0, cy1, cy2;  // phi, m of rows r-2 .. r
   T fS[9];                  // dt*alpha*fbar of the face below (north face of k-1)
   T PS, QSx, QSy;           // its collision part, see face_stage
-  // mass correction (MFIX): the stored f~_i lack w_i delta, delta being the
-  // per-cell correction set after the previous step; cw0..2 = w_i delta per
-  // weight class.  Per row group the lane sums the phi it writes (macc) and
-  // how much of the correction survived the rounding of f~_i + w_i delta to T
-  // as its own rows are loaded (oac0 / oac1 by group parity: loads run at most
-  // one group ahead of the faces); the group totals go to part_row[2 g + 0/1].
-  T cw0, cw1, cw2;
-  double macc, oac0, oac1;
+  // mass correction (MFIX): the stored f~_i of the cells whose stored f~_0 is
+  // below fitmax lack w_i delta, the correction set after the previous step;
+  // cw0..2 = w_i delta per weight class.  Per row group the lane sums the phi
+  // it writes (macc) and counts the cells it writes with f~_0 below
+  // MASS_FIT_MAX (mcnt), the cells the next correction goes to; the group
+  // totals go to part_row[2 g + 0 / 1].
+  T cw0, cw1, cw2, fitmax;
+  double macc, mcnt;
   double* part_row;
 
   __device__ __forceinline__ T cw(int i) const { return i == 0 ? cw0 : ((i & 1) ? cw1 : cw2); }
@@ -179,20 +179,14 @@ struct Marcher {
 
   __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) {
     const T* p = row_src(wrapi(row, a.ny));
-    T ce = T(0);
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-      const T raw = p[i * OWN];
-      d.f[i] = MFIX ? raw + cw(i) : raw;
-      if (MFIX) ce += d.f[i] - raw;   // the rounded increment: exact in T
+    for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
+    if (MFIX) {
+      const bool fit = d.f[0] < fitmax;
+#pragma unroll
+      for (int i = 0; i < 9; i++) d.f[i] = fit ? d.f[i] + cw(i) : d.f[i];
     }
     d.hp = p[9 * OWN];
-    if (MFIX && owned && row >= y0 && row < y1) {
-      if ((row / MASS_GROUP) & 1)
-        oac1 += (double)ce;
-      else
-        oac0 += (double)ce;
-    }
   }
 
   // phi = sum_i f~_i (Eq. 30, pairwise) of a new row and its horizontal
@@ -335,7 +329,7 @@ struct Marcher {
     // f~+ = fbar+ + kap (X - fbar+): X of row k is rebuilt from its phi and m
     // (held since its cell stage) instead of reading f~ of the row again.
     // Then f~^{n+1} = f~+ + dt L (Eq. 21).
-    double cs = 0.0;
+    double cs = 0.0, cf0 = 0.0;
     if (owned) {
       T x[9];
       collision_target(cp0, cx0, cy0, x);
@@ -347,7 +341,10 @@ struct Marcher {
         const T tfp = fma(a.kap, x[i] - bp, bp);
         const T v = tfp + out[i];
         __builtin_nontemporal_store(v, o + i * OWN);
-        if (MFIX) cs += (double)v;
+        if (MFIX) {
+          cs += (double)v;
+          if (i == 0 && v < T(MASS_FIT_MAX)) cf0 = 1.0;
+        }
       }
       __builtin_nontemporal_store(ph0, o + 9 * OWN);
     }
@@ -356,9 +353,9 @@ struct Marcher {
       // two segments (segments are whole groups), so its sum -- lanes in a
       // fixed butterfly after rows in order -- does not depend on the tiling
       macc += cs;
+      mcnt += cf0;
       if ((k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1) {
-        const bool odd = (k / MASS_GROUP) & 1;
-        double v = macc, w = odd ? oac1 : oac0;
+        double v = macc, w = mcnt;
 #pragma unroll
         for (int m = 1; m < LANES; m <<= 1) {
           v += __shfl_xor(v, m);
@@ -369,10 +366,7 @@ struct Marcher {
           part_row[2 * (k / MASS_GROUP) + 1] = w;
         }
         macc = 0.0;
-        if (odd)
-          oac1 = 0.0;
-        else
-          oac0 = 0.0;
+        mcnt = 0.0;
       }
     }
   }
@@ -391,7 +385,7 @@ struct Marcher {
 
   __device__ void run() {
     RowRegs<T> B, C;
-    macc = oac0 = oac1 = 0.0;
+    macc = mcnt = 0.0;
     cp0 = cp1 = cp2 = cx0 = cx1 = cx2 = cy0 = cy1 = cy2 = T(0);
     ph0 = ph1 = ph2 = ph3 = T(0);
     D0 = D1 = D2 = A0 = A1 = A2 = T(0);
@@ -412,14 +406,16 @@ struct Marcher {
 };
 
 // One tile: the strip `strip` of the grid, rows of segment `seg`, step n.
-// pend = per-cell mass correction delta still to apply to the stored f~ (MFIX).
+// pend = per-cell mass correction delta still to apply to the stored f~ of the
+// cells whose stored f~_0 is below fitmax (MFIX).
 template <typename T, int R, bool MFIX>
 __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
                                            const T* __restrict__ src, T* __restrict__ dst,
                                            const T* __restrict__ cf,
                                            const T* __restrict__ tabx,
                                            const T* __restrict__ taby,
-                                           double* __restrict__ part, double pend, int strip,
+                                           double* __restrict__ part, double pend,
+                                           double fitmax, int strip,
                                            int seg, T (*s_bfp)[9][LROW]) {
   Marcher<T, R, MFIX> m{a, src, dst, as_const(cf), tabx, as_const(taby), s_bfp};
   const int lane = threadIdx.x;
@@ -457,6 +453,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
     m.cw0 = T(wq(0) * pend);
     m.cw1 = T(wq(1) * pend);
     m.cw2 = T(wq(2) * pend);
+    m.fitmax = T(fitmax);
     m.part_row = part + 2 * (int64_t)strip * a.ngroups;
   }
   m.run();
@@ -482,7 +479,9 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void step_ke
   for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
   __syncthreads();
   const double pend = MFIX ? hdr->pending : 0.0;
-  march_tile<T, R, MFIX>(a, n, src, dst, cf, tabx, taby, part, pend, strip, seg, s_bfp);
+  const double fitmax = MFIX ? hdr->fit_max : 0.0;
+  march_tile<T, R, MFIX>(a, n, src, dst, cf, tabx, taby, part, pend, fitmax, strip, seg,
+                         s_bfp);
 }
 
 // Neumaier pair (sum, compensation)
@@ -496,22 +495,18 @@ __device__ __forceinline__ void neu_add(double& s, double& c, double v) {
 }
 
 // After a step with the fused correction.  The partials hold, per row group,
-// the new total (M^{n+1}) and the part of the last correction that survived
-// the rounding of f~_i + w_i delta to T, which is sigma N delta.  The next
-// correction is delta = (M0 - M^{n+1}) / (N sigma), so that what survives of
-// it restores M0.  sigma keeps its last value while the correction is too
-// small to measure.
+// the new total M^{n+1} and the number of new cells with f~_0 below
+// MASS_FIT_MAX.  A correction below half an ulp of f~_i is lost when it is
+// rounded into f~_i, so it goes where it is kept: to those cells (the phase
+// with phi near 0), delta = (M0 - M^{n+1}) / count; where fewer than 1 % of
+// the cells qualify, to every cell, delta = (M0 - M^{n+1}) / N.  What rounding
+// still loses is in the next step's total and corrected then.
 __device__ __forceinline__ void mass_fix_set(StateHeader* __restrict__ hdr, double m_new,
-                                             double survived, double ncells) {
-  const double applied = hdr->pending * ncells;
-  double sigma = hdr->sigma > 0.0 ? hdr->sigma : 1.0;
-  if (fabs(applied) > 1e-13 * fabs(hdr->mass0)) {
-    const double sv = survived / applied;
-    if (sv >= 0.0625 && sv <= 1.5) sigma = sv;
-  }
-  hdr->sigma = sigma;
+                                             double nfit, double ncells) {
+  const bool to_fit = nfit >= 0.01 * ncells && nfit >= 1.0;
+  hdr->fit_max = to_fit ? MASS_FIT_MAX : INFINITY;
   hdr->mass_now = m_new;
-  hdr->pending = (hdr->mass0 - m_new) / (ncells * sigma);
+  hdr->pending = (hdr->mass0 - m_new) / (to_fit ? nfit : ncells);
 }
 
 // Fixed-order (Neumaier) sum of n pairs (v[2j], v[2j+1]) by one wavefront:
@@ -667,8 +662,9 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
     const int seg = w.tile / a.nstrips;
     const int b = (int)(n & 1);
     const double pend = MFIX ? d->hdr->pending : 0.0;
+    const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
     march_tile<T, R, MFIX>(a, n, d->buf[b], d->buf[b ^ 1], d->cf, d->tabx, d->taby, d->part,
-                           pend, strip, seg, s_bfp);
+                           pend, fitmax, strip, seg, s_bfp);
     // the next item's ring starts from its own rows; order this tile's LDS
     // reads before them
     wave_sync();
@@ -738,11 +734,13 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ phi
-// f~_i of the state: the stored value plus the pending correction w_i delta,
-// rounded as the step kernel rounds it when it loads the value
+// f~_i of the state: the stored value, plus the pending correction w_i delta
+// if the cell's stored f~_0 is below the header's fit_max, rounded as the step
+// kernel rounds it when it loads the value
 template <typename T>
-__device__ __forceinline__ T stored_f(T v, int i, double pend) {
-  return pend != 0.0 ? v + T(wq(i) * pend) : v;
+__device__ __forceinline__ T stored_f(T v, int i, T f0, const StateHeader* hdr) {
+  const double pend = hdr->pending;
+  return (pend != 0.0 && f0 < T(hdr->fit_max)) ? v + T(wq(i) * pend) : v;
 }
 
 template <typename T>
@@ -753,10 +751,10 @@ __global__ __launch_bounds__(256) void phi_kernel(const T* __restrict__ buf, Til
   const int y = blockIdx.y;
   if (x >= tl.nx || y >= tl.ny) return;
   const int64_t o = tl.idx(0, y, x);
-  const double pend = hdr->pending;
-  T s = stored_f(buf[o], 0, pend);
+  const T f0 = buf[o];
+  T s = stored_f(f0, 0, f0, hdr);
 #pragma unroll
-  for (int i = 1; i < 9; i++) s += stored_f(buf[o + i * OWN], i, pend);
+  for (int i = 1; i < 9; i++) s += stored_f(buf[o + i * OWN], i, f0, hdr);
   out[(int64_t)y * tl.nx + x] = s;
 }
 
@@ -768,7 +766,8 @@ __global__ __launch_bounds__(256) void export_kernel(const T* __restrict__ buf, 
   const int y = blockIdx.y;
   const int i = blockIdx.z;
   if (x >= tl.nx || y >= tl.ny) return;
-  out[((int64_t)i * tl.ny + y) * tl.nx + x] = stored_f(buf[tl.idx(i, y, x)], i, hdr->pending);
+  out[((int64_t)i * tl.ny + y) * tl.nx + x] =
+      stored_f(buf[tl.idx(i, y, x)], i, buf[tl.idx(0, y, x)], hdr);
 }
 
 // ------------------------------------------------------------------ mass
@@ -784,7 +783,6 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
   __shared__ double ss[MASS_THREADS], sc[MASS_THREADS];
   const int nx = tl.nx;
   const int64_t N = (int64_t)nx * tl.ny;
-  const double pend = STATE ? hdr->pending : 0.0;
   double s = 0.0, c = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * MASS_THREADS + threadIdx.x; j < N;
        j += (int64_t)MASS_BLOCKS * MASS_THREADS) {
@@ -792,9 +790,10 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
     double v;
     if (STATE) {
       const int64_t o = tl.idx(0, y, x);
-      v = (double)stored_f(f[o], 0, pend);
+      const T f0 = f[o];
+      v = (double)stored_f(f0, 0, f0, hdr);
 #pragma unroll
-      for (int i = 1; i < 9; i++) v += (double)stored_f(f[o + i * OWN], i, pend);
+      for (int i = 1; i < 9; i++) v += (double)stored_f(f[o + i * OWN], i, f0, hdr);
     } else {
       v = (double)f[j];
     }

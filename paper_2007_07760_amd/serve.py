@@ -15,9 +15,11 @@ Host-side scheduling only: every step of every solve runs in libdugks.so.
 """
 from __future__ import annotations
 
+import argparse
 import collections
 import dataclasses
-import math
+import json
+import sys
 import time
 
 import numpy as np
@@ -147,11 +149,13 @@ class Server:
                      for _ in range(2)]
         self._ev = [torch.cuda.Event(), torch.cuda.Event()]
 
-    def run(self, trace: list, keep_phi=()) -> list[Result]:
+    def run(self, trace: list, keep_phi=(), progress=None) -> list[Result]:
         """Serve `trace` (requests with arrival times in seconds from the
         start); returns one Result per request, in id order.  phi is kept on
-        the host for the ids in `keep_phi`."""
+        the host for the ids in `keep_phi`; `progress(done, total)` is called
+        about every 30 s."""
         keep = set(keep_phi)
+        t_note = time.perf_counter()
         dev = self.device
         too_big = [r["id"] for r in trace if state_bytes(r) > self.pool.nbytes - ALIGN]
         if too_big:
@@ -238,6 +242,9 @@ class Server:
                     else:
                         still.append((jb, host, ev))
                 finishing = still
+                if progress and time.perf_counter() - t_note > 30.0:
+                    t_note = time.perf_counter()
+                    progress(len(results), len(trace))
         return [results[k] for k in sorted(results)]
 
 
@@ -249,10 +256,11 @@ def run_alone(req: dict, device="cuda") -> np.ndarray:
     return s.phi().cpu().numpy()
 
 
-def run_fifo(trace: list, keep_phi=(), device="cuda") -> list[Result]:
+def run_fifo(trace: list, keep_phi=(), device="cuda", progress=None) -> list[Result]:
     """The baseline: requests one at a time in arrival order, each with its
     own memory and per-step launches."""
     keep = set(keep_phi)
+    t_note = time.perf_counter()
     dev = torch.device(device)
     out = []
     t0 = time.perf_counter()
@@ -268,6 +276,9 @@ def run_fifo(trace: list, keep_phi=(), device="cuda") -> list[Result]:
                               r["nx"] * r["ny"], r["steps"],
                               phi if r["id"] in keep else None))
             del s
+            if progress and time.perf_counter() - t_note > 30.0:
+                t_note = time.perf_counter()
+                progress(len(out), len(trace))
     return sorted(out, key=lambda x: x.id)
 
 
@@ -280,3 +291,54 @@ def summary(results: list[Result]) -> dict:
                 makespan_s=t_last - t_first, p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
                 lattice_updates=int(lus))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description="Serve a synthetic request stream of "
+                                 "interface-tracking solves; print one JSON line.")
+    ap.add_argument("--count", type=int, default=1000)
+    ap.add_argument("--rate", type=float, default=200.0, help="mean arrivals per second")
+    ap.add_argument("--nmin", type=int, default=64)
+    ap.add_argument("--nmax", type=int, default=4096)
+    ap.add_argument("--smin", type=int, default=500)
+    ap.add_argument("--smax", type=int, default=20000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", choices=["batched", "fifo"], default="batched")
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--graph-steps", type=int, default=16)
+    ap.add_argument("--samples", type=int, default=16,
+                    help="requests whose result is compared with an alone run")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("serving needs a HIP device", file=sys.stderr)
+        return 2
+    trace = I.serve_trace(args.count, args.rate, args.nmin, args.nmax, args.smin, args.smax,
+                          args.seed)
+    step = max(1, len(trace) // max(1, args.samples))
+    sample = [r["id"] for r in trace[::step]][:args.samples]
+
+    def note(done, total):
+        print(f"progress {done}/{total}", file=sys.stderr, flush=True)
+
+    if args.mode == "batched":
+        srv = Server(args.slots, int(args.budget_gb * (1 << 30)), args.graph_steps)
+        res = srv.run(trace, keep_phi=sample, progress=note)
+        extra = {"pool_peak_gb": round(srv.pool.peak / (1 << 30), 3), "slots": args.slots,
+                 "graph_steps": args.graph_steps, "tile_rows": srv.batch.tile_rows}
+        del srv
+    else:
+        res = run_fifo(trace, keep_phi=sample, progress=note)
+        extra = {}
+    same = [r.id for r in res if r.phi is not None and
+            not np.array_equal(r.phi, run_alone(trace[r.id]))]
+    out = dict(summary(res), mode=args.mode, count=args.count, rate=args.rate,
+               sizes=[args.nmin, args.nmax], steps=[args.smin, args.smax], seed=args.seed,
+               samples_checked=len(sample), samples_differing=same, **extra)
+    print(json.dumps({k: (round(v, 4) if isinstance(v, float) else v)
+                      for k, v in out.items()}), flush=True)
+    return 0 if not same else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

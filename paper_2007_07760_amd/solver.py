@@ -38,7 +38,7 @@ class Solver:
 
     def __del__(self):
         plan = getattr(self, "plan", None)
-        if plan:
+        if plan and C is not None and C.dugks_plan_destroy is not None:
             C.dugks_plan_destroy(plan)
             self.plan = None
 
