@@ -1,0 +1,173 @@
+"""The paper's interface-tracking benchmarks (Sec. III) on the GPU path.
+
+Each experiment is defined by the paper's dimensionless parameters (Pe = U0 L0 / M,
+Cn = W / L0, one period T_f = L0 / U0) and measured with the L2 error of Eq. 41
+between the final and the initial order parameter.  A whole table -- grids of
+different sizes, CFL numbers and periods -- runs as one FP64 batch (one
+persistent kernel per step over every grid; each grid stops at its own
+period).
+
+  translation  Sec. III.A: circle R = L0/5 at the centre, u = (U0, U0), one
+               period T_f (Tables I-III).
+  zalesak      Sec. III.B: sharp slotted disk R = 0.4 L0 at the centre, slot
+               0.08 L0 wide pointing down, rotation with angular velocity
+               U0 pi / L0 about the centre, one turn 2 T_f; the final field is
+               cut by a step function before Eq. 41 (Tables IV-V).  The slot
+               depth is not given: 0.5 L0 from the bottom of the disk here.
+  deformation  Sec. III.D: circle at the centre (radius not given: L0/5 here),
+               u = -U0 sin(4 pi x/L0) sin(4 pi y/L0) cos(pi t/T_f),
+               v = -U0 cos(4 pi x/L0) cos(4 pi y/L0) cos(pi t/T_f); back at T_f
+               (Tables VIII-IX).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as C
+from . import inputs as I
+from .batch import Batch
+from .solver import Solver
+
+
+def translation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+    u0 = pe * m / n
+    tf = n / u0
+    return dict(kind="translation", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl,
+                recon=recon, vel_kind=C.VEL_UNIFORM, vel_param=(u0, u0),
+                steps=int(round(tf / cfl)),
+                phi0=lambda: I.tanh_circle(n, n, n / 2, n / 2, n / 5, cn * n))
+
+
+ZALESAK_SLOT_DEPTH = 0.5   # of L0, from the bottom of the disk (not given)
+
+
+def zalesak(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+    u0 = pe * m / n
+    omega = u0 * math.pi / n
+    return dict(kind="zalesak", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl, recon=recon,
+                vel_kind=C.VEL_ROTATION, vel_param=(omega, n / 2, n / 2),
+                steps=int(round(2 * n / u0 / cfl)),
+                phi0=lambda: I.slotted_disk(n, n, n / 2, n / 2, 0.4 * n, 0.08 * n,
+                                            ZALESAK_SLOT_DEPTH * n))
+
+
+DEFORMATION_RADIUS = 0.2   # of L0 (not given)
+
+
+def deformation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+    u0 = pe * m / n
+    tf = n / u0
+    return dict(kind="deformation", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl,
+                recon=recon, vel_kind=C.VEL_DEFORMATION, vel_param=(u0, tf),
+                steps=int(round(tf / cfl)),
+                phi0=lambda: I.tanh_circle(n, n, n / 2, n / 2, DEFORMATION_RADIUS * n, cn * n))
+
+
+def e_phi(phi: np.ndarray, phi0: np.ndarray) -> float:
+    """Eq. 41: relative L2 distance of phi from phi0."""
+    d = phi.astype(np.float64) - phi0
+    return float(np.sqrt(np.sum(d * d) / np.sum(phi0 * phi0)))
+
+
+def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float]:
+    """Run every configuration (one reconstruction) in one FP64 batch and
+    return E_phi of each after its own step count.  flags: plan flags
+    (DUGKS_FLAG_DTPHIU_ZERO drops d(phi u)/dt from the source)."""
+    if not configs:
+        return []
+    recon = configs[0]["recon"]
+    assert all(c["recon"] == recon for c in configs)
+    b = Batch(len(configs), C.F64, recon, 0)
+    sol, p0 = [], []
+    for k, c in enumerate(configs):
+        phi0 = c["phi0"]()
+        s = Solver(c["nx"], c["ny"], c["mobility"], c["width"], c["cfl"], recon=recon,
+                   precision=C.F64, vel_kind=c["vel_kind"], vel_param=c["vel_param"],
+                   flags=flags).init(phi0)
+        b.set(k, s, c["steps"])
+        sol.append(s)
+        p0.append(phi0)
+    b.commit()
+    left = max(c["steps"] for c in configs)
+    while left > 0:
+        chunk = min(left, 20 * graph_steps)
+        b.step(chunk, graph_steps=graph_steps)
+        left -= chunk
+    st = b.sync()
+    assert all(int(st[k, 0]) == c["steps"] for k, c in enumerate(configs))
+    out = []
+    for s, c, phi0 in zip(sol, configs, p0):
+        phi = s.phi().cpu().numpy()
+        if c["kind"] == "zalesak":
+            phi = (phi >= 0.5).astype(np.float64)   # step function of Sec. III.B
+        out.append(e_phi(phi, phi0))
+    del b, sol
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- the tables
+CFLS = (0.25, 0.5, 0.8)
+SCHEMES = {"T2S2CD": C.CENTRAL2, "T2S3": C.UPWIND3}
+
+
+def table_configs(table: str, scheme: str) -> tuple[list, list[dict]]:
+    """(column keys, configs in row-major order CFL x column) of a table."""
+    r = SCHEMES[scheme]
+    if table == "I":      # translation, N sweep, Pe = 128, Cn = 1/32, M = 0.02
+        cols = [128, 192, 256, 384, 512]
+        return cols, [translation(n, 128, 1 / 32, 0.02, c, r) for c in CFLS for n in cols]
+    if table == "II":     # translation, Pe sweep, L0 = 256, Cn = 4/256, M = 0.02
+        cols = [256, 512, 640, 819.2, 1024, 1280]
+        return cols, [translation(256, pe, 4 / 256, 0.02, c, r) for c in CFLS for pe in cols]
+    if table == "III":    # translation, M sweep, L0 = 256, Cn = 4/256, Pe = 256
+        cols = [0.01, 0.02, 0.04, 0.05, 0.064, 0.08, 0.1]
+        return cols, [translation(256, 256, 4 / 256, m, c, r) for c in CFLS for m in cols]
+    if table == "IV":     # Zalesak, Pe sweep, L0 = 256, Cn = 4/256, M = 0.02
+        cols = [256, 512, 640, 819.2, 1024, 1280]
+        return cols, [zalesak(256, pe, 4 / 256, 0.02, c, r) for c in CFLS for pe in cols]
+    if table == "V":      # Zalesak, M sweep, L0 = 256, Cn = 4/256, Pe = 256
+        cols = [0.01, 0.02, 0.04, 0.05, 0.064, 0.08, 0.1]
+        return cols, [zalesak(256, 256, 4 / 256, m, c, r) for c in CFLS for m in cols]
+    if table == "VIII":   # deformation, Pe sweep, L0 = 512, Cn = 4/512, M = 0.02
+        cols = [512, 1024, 1280, 1638.4, 2048, 2560]
+        return cols, [deformation(512, pe, 4 / 512, 0.02, c, r) for c in CFLS for pe in cols]
+    if table == "IX":     # deformation, M sweep, L0 = 512, Cn = 4/512, Pe = 512
+        cols = [0.01, 0.02, 0.04, 0.05, 0.064, 0.08, 0.1]
+        return cols, [deformation(512, 512, 4 / 512, m, c, r) for c in CFLS for m in cols]
+    raise KeyError(table)
+
+
+def run_table(table: str, scheme: str, flags: int = 0) -> dict:
+    cols, cfgs = table_configs(table, scheme)
+    e = run(cfgs, flags=flags)
+    return {f"CFL{c}": dict(zip([str(x) for x in cols], e[k * len(cols):(k + 1) * len(cols)]))
+            for k, c in enumerate(CFLS)}
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="Run the paper's DUGKS-T2 tables on the GPU and "
+                                 "print E_phi of every entry as JSON.")
+    ap.add_argument("tables", nargs="*", default=["I", "II", "III", "IV", "V", "VIII", "IX"])
+    ap.add_argument("--schemes", nargs="*", default=list(SCHEMES))
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("the paper tables need a HIP device", file=sys.stderr)
+        return 2
+    out = {}
+    for t in args.tables:
+        for s in args.schemes:
+            out[f"{t}/{s}"] = run_table(t, s)
+            print(f"table {t} {s} done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -1,0 +1,95 @@
+"""The paper's own benchmark numbers, reproduced on the GPU path.
+
+Sec. III prints the L2 error of Eq. 41 for every benchmark, scheme and CFL
+number (Tables I-V, VIII-IX); the DUGKS-T2S2CD (central-2) and DUGKS-T2S3
+(upwind-3) rows are this library's schemes.  The printed values are in
+tests/golden/paper_tables_t2.json.  Each table runs as one FP64 batch.
+
+What the comparison pins: the readings of the paper's unstated choices
+(isotropic stencils, tau = 3 M, the backward-difference d(phi u)/dt, the tie
+rule of the upwind faces, the first state) reproduce the authors' numbers --
+Tables I, II and VIII to within a few per cent.  Table III drifts to ~1.3 x
+at the largest mobility (d(phi u)/dt matters most there; without it the
+ratios reach 4.4).  Zalesak's slot depth and the deformation radius are not
+given; with the readings 0.5 L0 and L0/5 the tables agree to ~10 % and ~5 %.
+
+By default a subset runs (about a minute); DUGKS_PAPER_TABLES=full runs
+every entry of every table (about 8 minutes).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "paper_tables_t2.json")))
+FULL = os.environ.get("DUGKS_PAPER_TABLES") == "full"
+
+# (table, max |ratio - 1| allowed for every entry, columns of the default subset)
+TABLES = [
+    ("I", 0.03, [128]),
+    ("II", 0.10, [640, 819.2, 1024, 1280]),
+    ("III", 0.35, [0.04, 0.05, 0.064]),
+    ("IV", 0.12, [1024, 1280]),
+    ("V", 0.12, [0.08, 0.1]),
+    ("VIII", 0.03, [2048, 2560]),
+    ("IX", 0.05, [0.08, 0.1]),
+]
+
+
+@pytest.fixture(scope="module")
+def runs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2007_07760_amd import _lib
+    _lib.load()
+    from paper_2007_07760_amd import paper_runs
+    return paper_runs
+
+
+def _printed(table, scheme, cfl_key, col):
+    g = GOLD[table]
+    v = g[scheme][cfl_key][g["cols"].index(col)]
+    if table == "IX" and scheme == "T2S3" and cfl_key == "CFL0.5" and col == 0.1:
+        v = 9.55e-3   # printed 9.55e-2: a misprint (see the golden file's note)
+    return v
+
+
+@pytest.mark.parametrize("table,tol,subset", TABLES)
+@pytest.mark.parametrize("scheme", ["T2S2CD", "T2S3"])
+def test_paper_table(runs, table, tol, subset, scheme):
+    cols, cfgs = runs.table_configs(table, scheme)
+    keep = [k for k, c in enumerate(cfgs) if FULL or subset is None
+            or cols[k % len(cols)] in subset]
+    print(f"case table {table} {scheme}: {len(keep)} of {len(cfgs)} entries", flush=True)
+    e = runs.run([cfgs[k] for k in keep])
+    worst = 0.0
+    for val, k in zip(e, keep):
+        cfl_key = f"CFL{runs.CFLS[k // len(cols)]}"
+        col = cols[k % len(cols)]
+        ref = _printed(table, scheme, cfl_key, col)
+        r = val / ref
+        worst = max(worst, abs(r - 1.0))
+        print(f"  {table} {scheme} {cfl_key} {col}: gpu {val:.3e} paper {ref:.3e} "
+              f"ratio {r:.3f}", flush=True)
+    assert worst <= tol, worst
+
+
+def test_translation_trends_and_order(runs):
+    """Qualitative facts the paper states for Table I: second-order
+    convergence for both schemes; the upwind error falls as C rises."""
+    cols, cfgs = runs.table_configs("I", "T2S3")
+    pick = [k for k, c in enumerate(cfgs) if cols[k % len(cols)] in (128, 192)]
+    e = dict(zip(pick, runs.run([cfgs[k] for k in pick])))
+    n = len(cols)
+    for row in range(3):
+        e128, e192 = e[row * n + 0], e[row * n + 1]
+        order = np.log(e128 / e192) / np.log(1.5)
+        print(f"  T2S3 CFL{runs.CFLS[row]} order 128->192: {order:.2f}", flush=True)
+        assert 1.5 < order < 3.2
+    for col in (0, 1):
+        assert e[0 * n + col] > e[1 * n + col] > e[2 * n + col]
