@@ -84,6 +84,18 @@ typedef enum {
   DUGKS_VEL_ARRAYS = 4
 } dugks_vel_kind;
 
+/* Time discretisation:
+ *  T2    the original two-level DUGKS (Sec. II.B.1): the state stores
+ *        f~ = f - (dt/2)(Omega + S); one face reconstruction per step at
+ *        t + dt/2.
+ *  T3S3  the third-order DUGKS of Sec. II.B.2: the state stores
+ *        f^ = f - (dt/4)(Omega + S); two reconstructions per step, at
+ *        t + dt/6 from fbar+ at t (Eq. 31) and at t + 3dt/4 from fbar+ at
+ *        t + dt/3 (Eq. 34), combined by Eq. 16.  Needs dt < 12 tau (the
+ *        coefficient of f^ in Eq. 31 must stay positive); d(phi u)/dt at
+ *        t + dt/3 is the difference quotient over [t, t + dt/3]. */
+typedef enum { DUGKS_T2 = 0, DUGKS_T3S3 = 1 } dugks_scheme;
+
 /* flags */
 #define DUGKS_FLAG_DTPHIU_ZERO 1u /* drop d(phi u)/dt from the source (test hook) */
 /* Fused mass correction (meant for FP32 plans): every step also sums
@@ -109,15 +121,16 @@ typedef struct {
   int32_t flags;           /* DUGKS_FLAG_*                                       */
   double vel_param[6];     /* p0.. of the velocity kind; finite                  */
   int32_t tile_rows;       /* rows one wavefront marches; 0 = library default    */
-  int32_t reserved;        /* must be 0                                          */
+  int32_t scheme;          /* dugks_scheme                                       */
 } dugks_params;
 
 typedef struct dugks_plan dugks_plan;
 
 /* Validate p and build an immutable plan (stencil coefficients of the chosen
  * reconstruction, collision coefficients, launch geometry).  Host-only: no HIP
- * call is made.  Errors: EINVAL (p or out NULL, a field out of range),
- * EUNSUPPORTED (ARRAYS velocity), ENOMEM. */
+ * call is made.  Errors: EINVAL (p or out NULL, a field out of range, T3S3
+ * with dt >= 12 tau), EUNSUPPORTED (ARRAYS velocity; T3S3 with
+ * DUGKS_FLAG_MASS_FIX), ENOMEM. */
 int dugks_plan_create(const dugks_params *p, dugks_plan **out);
 void dugks_plan_destroy(dugks_plan *plan);
 
@@ -134,19 +147,22 @@ size_t dugks_state_bytes(const dugks_plan *plan);
 int dugks_init(const dugks_plan *plan, void *state, const double *phi0_dev,
                void *stream);
 
-/* Advance the state from step `step` by `nsteps` T2 steps (Eqs. 21-28 with the
- * Eq. 15 update form): one fused face-reconstruction + flux + update kernel per
- * step.  Asynchronous on `stream`.  Errors: EINVAL (NULL, step < 0,
- * nsteps < 0), EDEVICE. */
+/* Advance the state from step `step` by `nsteps` steps of the plan's scheme:
+ * T2 (Eqs. 21-28 with the Eq. 15 update form) is one fused
+ * face-reconstruction + flux + update kernel per step; T3S3 two such kernels
+ * (stages at t + dt/6 and t + 3 dt/4).  Asynchronous on `stream`.  Errors:
+ * EINVAL (NULL, step < 0, nsteps < 0), EDEVICE. */
 int dugks_step(const dugks_plan *plan, void *state, int64_t step,
                int64_t nsteps, void *stream);
 
-/* phi = sum_i f~_i (Eq. 30) of the state at `step`, written to phi_out_dev as
- * [ny][nx] dense elements of the plan's precision.  Asynchronous. */
+/* phi = sum_i of the stored distributions (Eq. 30; Eq. 30a for T3S3) of the
+ * state at `step`, written to phi_out_dev as [ny][nx] dense elements of the
+ * plan's precision.  Asynchronous. */
 int dugks_phi(const dugks_plan *plan, const void *state, int64_t step,
               void *phi_out_dev, void *stream);
 
-/* The 9 distributions f~_i of the state at `step`, written to out_dev as
+/* The 9 stored distributions (f~_i for T2, f^_i for T3S3) of the state at
+ * `step`, written to out_dev as
  * [9][ny][nx] dense elements of the plan's precision (velocity-major, paper
  * order of Sec. II.B.2).  Asynchronous.  Errors: EINVAL, EDEVICE. */
 int dugks_distributions(const dugks_plan *plan, const void *state, int64_t step,
@@ -203,7 +219,8 @@ void dugks_batch_destroy(dugks_batch *batch);
 /* Attach `state` (initialised by dugks_init for `plan`, currently at `step`)
  * to `slot`; the grid advances until its counter reaches `target` (>= step).
  * Replaces whatever the slot held.  Errors: EINVAL (range, NULL, misaligned
- * state, plan of another precision / reconstruction / mass-fix flag). */
+ * state, plan of another precision / reconstruction / mass-fix flag),
+ * EUNSUPPORTED (T3S3 plans: batches run T2 only). */
 int dugks_batch_set(dugks_batch *batch, int32_t slot, const dugks_plan *plan,
                     void *state, int64_t step, int64_t target);
 /* Empty `slot`.  Errors: EINVAL. */

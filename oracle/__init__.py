@@ -31,6 +31,7 @@ _FLAGS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]
 _LIB = _LIBS["plain"]
 
 CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
+T2, T3S3 = 0, 1
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
 
 
@@ -61,6 +62,7 @@ class _Params(ctypes.Structure):
         ("vel_param", ctypes.c_double * 6),
         ("u_arr", ctypes.c_void_p), ("v_arr", ctypes.c_void_p),
         ("dtphiu_zero", ctypes.c_int),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -112,6 +114,7 @@ class Params:
     u_arr: np.ndarray | None = None
     v_arr: np.ndarray | None = None
     dtphiu_zero: bool = False
+    scheme: int = 0          # T2 (0) or T3S3 (1)
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Params:
@@ -128,6 +131,7 @@ class Params:
             self._keep[:] = [u, v]
             p.u_arr, p.v_arr = u.ctypes.data, v.ctypes.data
         p.dtphiu_zero = int(self.dtphiu_zero)
+        p.scheme = int(self.scheme)
         return p
 
 

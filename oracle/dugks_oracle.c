@@ -42,6 +42,11 @@ static const double RT = 1.0 / 3.0;
 /* Guard of n = g / |g| where the gradient vanishes (reading: continuous cap). */
 static const double NORMAL_EPS = 1e-12;
 
+/* Grids below this many cells run their loops on one thread: the fork / join
+ * of a parallel region costs more than their work (and every cell's value is
+ * the same either way -- no loop here is a reduction). */
+#define PAR_MIN_CELLS 8192L
+
 /* Eq. (4) with phiA = 1, phiB = 0; W = +inf turns the term off. */
 static double theta_of(double phi, double width) {
   const double phiA = 1.0, phiB = 0.0;
@@ -172,7 +177,7 @@ static void hess_at(int nx, int ny, const double *a, int x, int y, double *hxx,
 }
 
 void oracle_grad(int nx, int ny, const double *a, double *gx, double *gy) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++)
       grad_at(nx, ny, a, x, y, &gx[IDX(nx, x, y)], &gy[IDX(nx, x, y)]);
@@ -180,7 +185,7 @@ void oracle_grad(int nx, int ny, const double *a, double *gx, double *gy) {
 
 void oracle_hess(int nx, int ny, const double *a, double *hxx, double *hxy,
                  double *hyy) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++)
       hess_at(nx, ny, a, x, y, &hxx[IDX(nx, x, y)], &hxy[IDX(nx, x, y)],
@@ -291,12 +296,12 @@ static double face_value(const oracle_params *p, const deriv_planes *d, int i,
   return F - h * (en * dn + et * dt);
 }
 
-/* buf: 5 planes of scratch for the derivatives (upwind only). */
-static void reconstruct_buf(const oracle_params *p, const double *bfp,
-                            double *bf_x, double *bf_y, double *buf) {
+/* buf: 5 planes of scratch for the derivatives (upwind only); h: the time the
+ * characteristic is traced back over. */
+static void reconstruct_h(const oracle_params *p, const double *bfp, double h,
+                          double *bf_x, double *bf_y, double *buf) {
   int nx = p->nx, ny = p->ny;
   size_t N = (size_t)nx * ny;
-  double h = 0.5 * p->cfl;
   for (int i = 0; i < 9; i++) {
     deriv_planes d = {bfp + i * N, NULL, NULL, NULL, NULL, NULL};
     if (p->recon == ORC_UPWIND3) {
@@ -307,13 +312,18 @@ static void reconstruct_buf(const oracle_params *p, const double *bfp,
       oracle_hess(nx, ny, d.f, hxx, hxy, hyy);
       d.gx = gx; d.gy = gy; d.hxx = hxx; d.hxy = hxy; d.hyy = hyy;
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
     for (int y = 0; y < ny; y++)
       for (int x = 0; x < nx; x++) {
         bf_x[i * N + IDX(nx, x, y)] = face_value(p, &d, i, x, y, 1, 0, h);
         bf_y[i * N + IDX(nx, x, y)] = face_value(p, &d, i, x, y, 0, 1, h);
       }
   }
+}
+
+static void reconstruct_buf(const oracle_params *p, const double *bfp,
+                            double *bf_x, double *bf_y, double *buf) {
+  reconstruct_h(p, bfp, 0.5 * p->cfl, bf_x, bf_y, buf);
 }
 
 void oracle_reconstruct(const oracle_params *p, const double *bfp,
@@ -402,7 +412,7 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
   /* 2. n = grad phi / |grad phi| (Eq. 2) with the isotropic gradient, and
    *    theta = -4 (phi - phiA)(phi - phiB) / (W (phiA - phiB)) (Eq. 4),
    *    phiA = 1, phiB = 0. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
@@ -417,7 +427,7 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
 
   /* 3. d(phi u)/dt at cell centres: backward difference over the last step,
    *    zero on the first step (reading; Eq. 14b leaves it open). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
@@ -434,7 +444,7 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
     }
 
   /* 4.-5. feq, S (Eq. 14) and the cell-centred f~+ (Eq. 9), fbar+ (Eq. 23). */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
@@ -462,7 +472,7 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
   for (int dir = 0; dir < 2; dir++) {
     const double *bf = dir == 0 ? bf_x : bf_y;
     double *fb = dir == 0 ? fb_x : fb_y;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
     for (int y = 0; y < ny; y++)
       for (int x = 0; x < nx; x++) {
         size_t c = IDX(nx, x, y);
@@ -483,7 +493,7 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
 
   /* 8. Meso-flux L(f_i) = (1/|V|) sum over faces of (xi_i . n_in) f |face|
    *    (Eq. 21, inward normals, |V| = |face| = 1) and f~^{n+1} = f~+ + dt L. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
@@ -503,8 +513,142 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
   memcpy(phi_now, phi, N * sizeof(double));
 }
 
+/* ---------------------------------------------------------------- T3S3
+ * DUGKS-T3S3 (Sec. II.B.2): the stored variable is f^ = f - (dt/4)(Omega + S);
+ * each step reconstructs the faces twice, at t_n + dt/6 and at t_n + 3 dt/4,
+ * from fbar+ built at t_n and at t' = t_n + dt/3. */
+
+/* Normal, theta, d(phi u)/dt, feq and S at the cell centres at time t, from
+ * phi at t; d(phi u)/dt = (phi u(t) - phi_ref u(t_ref)) / (t - t_ref), or 0. */
+static void cell_terms(const oracle_params *p, const double *phi, double t,
+                       const double *phi_ref, double t_ref, int with_j,
+                       double *feq, double *src) {
+  const int nx = p->nx, ny = p->ny;
+  const size_t N = (size_t)nx * ny;
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      size_t c = IDX(nx, x, y);
+      double gx, gy;
+      grad_at(nx, ny, phi, x, y, &gx, &gy);
+      double g = sqrt(gx * gx + gy * gy);
+      double d = g > NORMAL_EPS ? g : NORMAL_EPS;
+      double u, v, jx = 0.0, jy = 0.0, fe[9], sr[9];
+      cell_velocity(p, x, y, t, &u, &v);
+      if (with_j && !p->dtphiu_zero) {
+        double u0, v0;
+        cell_velocity(p, x, y, t_ref, &u0, &v0);
+        jx = (phi[c] * u - phi_ref[c] * u0) / (t - t_ref);
+        jy = (phi[c] * v - phi_ref[c] * v0) / (t - t_ref);
+      }
+      oracle_feq_source(phi[c], u, v, theta_of(phi[c], p->width), gx / d, gy / d, jx,
+                        jy, fe, sr);
+      for (int i = 0; i < 9; i++) {
+        feq[i * N + c] = fe[i];
+        src[i * N + c] = sr[i];
+      }
+    }
+}
+
+/* Meso-flux of one stage: fbar(x_b, t + hs) = fbar+(x_b - xi hs, t) on every
+ * face (Eqs. 24-26 with the stage's own half step hs), phi_b = sum_i fbar_i,
+ * feq_b from u(x_b, t + hs), S_b = mean of the two cells' S at t, f_b from
+ * Eq. 27 with hs, and L_i = sum over the faces of (xi_i . n_in) f_b (Eq. 21).
+ * scratch: 4 x 9 + 5 planes. */
+static void meso_flux(const oracle_params *p, const double *bfp, double hs, double t,
+                      const double *src, double *L, double *scratch) {
+  const int nx = p->nx, ny = p->ny;
+  const size_t N = (size_t)nx * ny;
+  const double tau = p->mobility / RT;
+  double *bf_x = scratch, *bf_y = scratch + 9 * N;
+  double *fb_x = scratch + 18 * N, *fb_y = scratch + 27 * N;
+  reconstruct_h(p, bfp, hs, bf_x, bf_y, scratch + 36 * N);
+  for (int dir = 0; dir < 2; dir++) {
+    const double *bf = dir == 0 ? bf_x : bf_y;
+    double *fb = dir == 0 ? fb_x : fb_y;
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
+    for (int y = 0; y < ny; y++)
+      for (int x = 0; x < nx; x++) {
+        size_t c = IDX(nx, x, y);
+        size_t r = dir == 0 ? IDX(nx, wrap(x + 1, nx), y) : IDX(nx, x, wrap(y + 1, ny));
+        double phib = 0.0;
+        for (int i = 0; i < 9; i++) phib += bf[i * N + c];
+        double ub, vb;
+        face_velocity(p, x, y, dir, t + hs, &ub, &vb);
+        for (int i = 0; i < 9; i++) {
+          double feqb = WQ[i] * phib * (1.0 + (EX[i] * ub + EY[i] * vb) / RT);
+          double sb = 0.5 * (src[i * N + c] + src[i * N + r]);
+          fb[i * N + c] = oracle_aux_shift(bf[i * N + c], 0.5 * hs, 0.0, feqb, sb, tau);
+        }
+      }
+  }
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
+  for (int y = 0; y < ny; y++)
+    for (int x = 0; x < nx; x++) {
+      size_t c = IDX(nx, x, y);
+      size_t w = IDX(nx, wrap(x - 1, nx), y);
+      size_t s = IDX(nx, x, wrap(y - 1, ny));
+      for (int i = 0; i < 9; i++)
+        L[i * N + c] = (-EX[i]) * fb_x[i * N + c] + (+EX[i]) * fb_x[i * N + w] +
+                       (-EY[i]) * fb_y[i * N + c] + (+EY[i]) * fb_y[i * N + s];
+    }
+}
+
+static int t3s3_step(const oracle_params *p, long n, const double *fh,
+                     const double *phi_prev, double *fh_next, double *phi_now) {
+  const int nx = p->nx, ny = p->ny;
+  const size_t N = (size_t)nx * ny;
+  const double dt = p->cfl;
+  const double tau = p->mobility / RT;
+  const double tn = n * dt, t1 = tn + dt / 3.0;
+  /* 2 x N, 11 x 9N, 41 x N of flux scratch */
+  double *blk = malloc((2 * N + 11 * 9 * N + 41 * N) * sizeof(double));
+  if (!blk) return 1;
+  double *phi = blk, *phi1 = phi + N;
+  double *feq = phi1 + N, *src = feq + 9 * N, *bfpA = src + 9 * N, *L1 = bfpA + 9 * N;
+  double *tfm = L1 + 9 * N, *feq1 = tfm + 9 * N, *src1 = feq1 + 9 * N;
+  double *bfpB = src1 + 9 * N, *L2 = bfpB + 9 * N, *fn = L2 + 9 * N, *q1 = fn + 9 * N;
+  double *scratch = q1 + 9 * N;
+
+  /* (i) phi at t_n from f^ (Eq. 30a); feq and S at t_n; fbar+ with half step
+   *     dt/6 from f^ (Eq. 31); faces at t_n + dt/6 and L(f*). */
+  oracle_phi(nx, ny, fh, phi);
+  cell_terms(p, phi, tn, phi_prev, tn - dt, n > 0, feq, src);
+  for (size_t k = 0; k < 9 * N; k++) {
+    bfpA[k] = oracle_aux_shift(fh[k], 0.25 * dt, dt / 12.0, feq[k], src[k], tau);
+    fn[k] = oracle_aux_shift(fh[k], 0.25 * dt, 0.0, feq[k], src[k], tau);   /* Eq. 32 */
+  }
+  meso_flux(p, bfpA, dt / 6.0, tn, src, L1, scratch);
+
+  /* (ii) f~+ at t_n (Eq. 33) and f~ at t' = t_n + dt/3 (Eq. 15); phi at t'
+   *      (Eq. 30b); feq, S at t' with d(phi u)/dt over [t_n, t'] (reading);
+   *      Omega + S at t' (Eq. 29, read with the factor 6 / (6 tau + dt)). */
+  for (size_t k = 0; k < 9 * N; k++) {
+    double tfp = oracle_aux_shift(fh[k], 0.25 * dt, dt / 6.0, feq[k], src[k], tau);
+    tfm[k] = tfp + dt / 3.0 * L1[k];
+  }
+  oracle_phi(nx, ny, tfm, phi1);
+  cell_terms(p, phi1, t1, phi, tn, 1, feq1, src1);
+  for (size_t k = 0; k < 9 * N; k++)
+    q1[k] = -6.0 / (6.0 * tau + dt) * (tfm[k] - feq1[k] - tau * src1[k]);
+
+  /* (iii) fbar+ with half step 5 dt/12 from f~ at t' (Eq. 34); faces at
+   *       t_n + 3 dt/4 and L(f**). */
+  for (size_t k = 0; k < 9 * N; k++)
+    bfpB[k] = oracle_aux_shift(tfm[k], dt / 6.0, 5.0 * dt / 24.0, feq1[k], src1[k], tau);
+  meso_flux(p, bfpB, 5.0 * dt / 12.0, t1, src1, L2, scratch);
+
+  /* (iv) f^ at t_{n+1} (Eq. 16) from f at t_n (Eq. 32). */
+  for (size_t k = 0; k < 9 * N; k++)
+    fh_next[k] = fn[k] + 0.75 * dt * q1[k] + dt / 7.0 * (3.0 * L1[k] + 4.0 * L2[k]);
+  memcpy(phi_now, phi, N * sizeof(double));
+  free(blk);
+  return 0;
+}
+
 int oracle_step(const oracle_params *p, long n, const double *tf,
                 const double *phi_prev, double *tf_next, double *phi_now) {
+  if (p->scheme == ORC_T3S3) return t3s3_step(p, n, tf, phi_prev, tf_next, phi_now);
   workspace ws;
   if (ws_alloc(&ws, (size_t)p->nx * p->ny)) return 1;
   step_ws(p, n, tf, phi_prev, tf_next, phi_now, &ws);
@@ -512,14 +656,16 @@ int oracle_step(const oracle_params *p, long n, const double *tf,
   return 0;
 }
 
-/* Reading of the first state: f = feq at t = 0, so f~ = feq - (dt/2)(Omega + S)
- * = feq - (dt/2) S with d(phi u)/dt = 0. */
+/* Reading of the first state: f = feq at t = 0, so Omega = 0 and the stored
+ * variable is feq - a S with d(phi u)/dt = 0: a = dt/2 for f~ (T2), dt/4 for
+ * f^ (T3S3). */
 int oracle_init(const oracle_params *p, const double *phi0, double *tf,
                 double *phi_hist) {
   const int nx = p->nx, ny = p->ny;
   const size_t N = (size_t)nx * ny;
   const double dt = p->cfl;
-#pragma omp parallel for schedule(static)
+  const double a = p->scheme == ORC_T3S3 ? 0.25 * dt : 0.5 * dt;
+#pragma omp parallel for schedule(static) if ((long)nx * ny >= PAR_MIN_CELLS)
   for (int y = 0; y < ny; y++)
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
@@ -531,7 +677,7 @@ int oracle_init(const oracle_params *p, const double *phi0, double *tf,
       double u, v, fe[9], sr[9];
       cell_velocity(p, x, y, 0.0, &u, &v);
       oracle_feq_source(phi0[c], u, v, theta, gx / d, gy / d, 0.0, 0.0, fe, sr);
-      for (int i = 0; i < 9; i++) tf[i * N + c] = fe[i] - 0.5 * dt * sr[i];
+      for (int i = 0; i < 9; i++) tf[i * N + c] = fe[i] - a * sr[i];
       phi_hist[c] = phi0[c];
     }
   return 0;
@@ -549,7 +695,16 @@ int oracle_run(const oracle_params *p, long n0, long nsteps, double *tf,
     return 1;
   }
   for (long k = 0; k < nsteps; k++) {
-    step_ws(p, n0 + k, tf, phi_hist, tf2, ph2, &ws);
+    if (p->scheme == ORC_T3S3) {
+      if (t3s3_step(p, n0 + k, tf, phi_hist, tf2, ph2)) {
+        free(ws.block);
+        free(tf2);
+        free(ph2);
+        return 1;
+      }
+    } else {
+      step_ws(p, n0 + k, tf, phi_hist, tf2, ph2, &ws);
+    }
     memcpy(tf, tf2, 9 * N * sizeof(double));
     memcpy(phi_hist, ph2, N * sizeof(double));
   }

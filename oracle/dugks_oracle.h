@@ -20,6 +20,7 @@ extern "C" {
 #endif
 
 enum { ORC_CENTRAL2 = 0, ORC_UPWIND3 = 1, ORC_CENTRAL4 = 2 };
+enum { ORC_T2 = 0, ORC_T3S3 = 1 };
 enum { ORC_VEL_UNIFORM = 0, ORC_VEL_ROTATION = 1, ORC_VEL_SINGLE_VORTEX = 2,
        ORC_VEL_DEFORMATION = 3, ORC_VEL_ARRAYS = 4 };
 
@@ -34,6 +35,8 @@ typedef struct {
   const double *u_arr;   /* ORC_VEL_ARRAYS: cell-centred u, [y][x]                  */
   const double *v_arr;   /* ORC_VEL_ARRAYS: cell-centred v, [y][x]                  */
   int dtphiu_zero;       /* 1: drop the d(phi u)/dt part of the source (test hook)  */
+  int scheme;            /* ORC_T2 (stored f~, Sec. II.B.1) or ORC_T3S3 (stored f^,
+                            Sec. II.B.2)                                             */
 } oracle_params;
 
 /* Prescribed velocity at point (x, y) and time t (analytic kinds only). */
@@ -64,11 +67,13 @@ double oracle_aux_shift(double g, double a, double b, double feq, double src,
 void oracle_reconstruct(const oracle_params *p, const double *bfp,
                         double *bf_x, double *bf_y);
 
-/* One T2 step n -> n+1: reads f~^n and phi^{n-1}, writes f~^{n+1} and phi^n. */
+/* One step n -> n+1 of the plan's scheme: reads the stored distributions
+ * (T2: f~^n; T3S3: f^^n) and phi^{n-1}, writes those of n+1 and phi^n. */
 int oracle_step(const oracle_params *p, long n, const double *tf,
                 const double *phi_prev, double *tf_next, double *phi_now);
 
-/* Initial state: f~^0 = feq - (dt/2) S^0 with d(phi u)/dt = 0; phi_hist = phi0. */
+/* Initial state from f = feq at t = 0 with d(phi u)/dt = 0: T2 f~^0 = feq -
+ * (dt/2) S^0, T3S3 f^^0 = feq - (dt/4) S^0; phi_hist = phi0. */
 int oracle_init(const oracle_params *p, const double *phi0, double *tf,
                 double *phi_hist);
 

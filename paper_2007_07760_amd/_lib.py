@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = range(6)
 F64, F32 = 0, 1
 CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
+T2, T3S3 = 0, 1
 FLAG_DTPHIU_ZERO = 1
 FLAG_MASS_FIX = 2
 
@@ -37,7 +38,7 @@ class dugks_params(ctypes.Structure):
         ("recon", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("vel_kind", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("vel_param", ctypes.c_double * 6),
-        ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("scheme", ctypes.c_int32),
     ]
 
 
@@ -106,7 +107,7 @@ def _check(rc: int, where: str) -> None:
 
 def make_params(nx, ny, mobility, width, cfl, recon=UPWIND3, precision=F64,
                 vel_kind=VEL_UNIFORM, vel_param=(0.0, 0.0), flags=0,
-                tile_rows=0) -> dugks_params:
+                tile_rows=0, scheme=0) -> dugks_params:
     p = dugks_params()
     p.nx, p.ny = int(nx), int(ny)
     p.mobility, p.width, p.cfl = float(mobility), float(width), float(cfl)
@@ -116,7 +117,7 @@ def make_params(nx, ny, mobility, width, cfl, recon=UPWIND3, precision=F64,
     for k in range(6):
         p.vel_param[k] = float(vp[k])
     p.tile_rows = int(tile_rows)
-    p.reserved = 0
+    p.scheme = int(scheme)
     return p
 
 

@@ -185,13 +185,17 @@ int validate(const dugks_params* p) {
   if (p->precision < 0 || p->precision > 1) return DUGKS_EINVAL;
   if (p->vel_kind < 0 || p->vel_kind > 4) return DUGKS_EINVAL;
   if (p->flags & ~(DUGKS_FLAG_DTPHIU_ZERO | DUGKS_FLAG_MASS_FIX)) return DUGKS_EINVAL;
-  if (p->tile_rows < 0 || p->tile_rows > 65536 || p->reserved != 0) return DUGKS_EINVAL;
+  if (p->tile_rows < 0 || p->tile_rows > 65536) return DUGKS_EINVAL;
+  if (p->scheme != DUGKS_T2 && p->scheme != DUGKS_T3S3) return DUGKS_EINVAL;
+  // T3S3: the coefficient (12 tau - dt) of f^ in Eq. 31 must stay positive
+  if (p->scheme == DUGKS_T3S3 && !(p->cfl < 12.0 * (p->mobility / RT))) return DUGKS_EINVAL;
   for (int k = 0; k < 6; k++)
     if (!finite(p->vel_param[k])) return DUGKS_EINVAL;
   if ((p->vel_kind == DUGKS_VEL_SINGLE_VORTEX || p->vel_kind == DUGKS_VEL_DEFORMATION) &&
       !(p->vel_param[1] > 0.0))
     return DUGKS_EINVAL;
   if (p->vel_kind == DUGKS_VEL_ARRAYS) return DUGKS_EUNSUPPORTED;
+  if (p->scheme == DUGKS_T3S3 && (p->flags & DUGKS_FLAG_MASS_FIX)) return DUGKS_EUNSUPPORTED;
   return DUGKS_OK;
 }
 
@@ -220,18 +224,28 @@ int default_tile_rows(const dugks_params& p, int nstrips) {
 }
 
 // ------------------------------------------------------------ launches
-template <typename T, bool MFIX>
-int launch_step_t(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+template <typename T, bool MFIX, int STAGE>
+int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
   const Layout& L = P->L;
-  StepArgs<T> a = step_args<T>(P);
+  StepArgs<T> a = step_args<T>(P, STAGE);
   StepBufs<T> q = step_bufs<T>(P, state, n);
+  T* dst2 = nullptr;
+  const T* aux = nullptr;
+  if (STAGE == STAGE_A) {           // f^^n -> f~(t'), Q
+    q.dst = at<T>(state, L.off_mid);
+    dst2 = at<T>(state, L.off_q);
+  } else if (STAGE == STAGE_B) {    // f~(t'), Q -> f^^{n+1}
+    q.src = at<T>(state, L.off_mid);
+    aux = at<T>(state, L.off_q);
+    q.cf = at<T>(state, L.off_coef2);
+  }
   double* part = at<double>(state, L.off_groups);
   StateHeader* hd = at<StateHeader>(state, 0);
   const int per = (a.nlogical + 7) / 8;
   dim3 grid(per * 8), block(LANES);
-#define DUGKS_LAUNCH(RR)                                                                      \
-  hipLaunchKernelGGL((step_kernel<T, RR, MFIX>), grid, block, 0, s, a, n, q.src, q.dst, q.cf, \
-                     q.tabx, q.taby, part, hd)
+#define DUGKS_LAUNCH(RR)                                                                       \
+  hipLaunchKernelGGL((step_kernel<T, RR, MFIX, STAGE>), grid, block, 0, s, a, n, q.src, q.dst, \
+                     dst2, aux, q.cf, q.tabx, q.taby, part, hd)
   switch (P->p.recon) {
     case DUGKS_CENTRAL2: DUGKS_LAUNCH(DUGKS_CENTRAL2); break;
     case DUGKS_UPWIND3: DUGKS_LAUNCH(DUGKS_UPWIND3); break;
@@ -247,8 +261,12 @@ int launch_step_t(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
 
 template <typename T>
 int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
-  return (P->p.flags & DUGKS_FLAG_MASS_FIX) ? launch_step_t<T, true>(P, state, n, s)
-                                           : launch_step_t<T, false>(P, state, n, s);
+  if (P->p.scheme == DUGKS_T3S3) {
+    int rc = launch_stage<T, false, STAGE_A>(P, state, n, s);
+    return rc ? rc : launch_stage<T, false, STAGE_B>(P, state, n, s);
+  }
+  return (P->p.flags & DUGKS_FLAG_MASS_FIX) ? launch_stage<T, true, STAGE_T2>(P, state, n, s)
+                                           : launch_stage<T, false, STAGE_T2>(P, state, n, s);
 }
 
 template <typename T>
@@ -264,9 +282,14 @@ int stage_head(const dugks_plan* P) {
   hd->precision = P->p.precision;
   hd->recon = P->p.recon;
   hd->fit_max = INFINITY;
-  // the device table carries dt * alpha (Eq. 27) times the stencil
+  // the device tables carry dt * alpha (Eq. 27 with the stage's half step)
+  // times the stencil
+  const int s0 = P->p.scheme == DUGKS_T3S3 ? STAGE_A : STAGE_T2;
   T* cf = at<T>(h, L.off_coef);
-  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->alpha * P->compact[k]);
+  for (int k = 0; k < NCOMPACT; k++) cf[k] = T(P->dt * P->st[s0].alpha * P->compact[k]);
+  T* cf2 = at<T>(h, L.off_coef2);
+  for (int k = 0; k < NCOMPACT; k++)
+    cf2[k] = T(P->dt * P->st[STAGE_B].alpha * P->compact2[k]);
   T* tx = at<T>(h, L.off_tabx);
   for (size_t k = 0; k < P->tabx.size(); k++) tx[k] = T(P->tabx[k]);
   T* ty = at<T>(h, L.off_taby);
@@ -290,7 +313,7 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   a.tabx = at<T>(state, L.off_tabx);
   a.taby = at<T>(state, L.off_taby);
   a.tl = L.tl;
-  a.dt = P->dt;
+  a.shift = P->p.scheme == DUGKS_T3S3 ? 0.25 * P->dt : 0.5 * P->dt;
   a.kth = isfinite(P->p.width) ? 4.0 / P->p.width : 0.0;
   dim3 grid((nx + 255) / 256, ny), block(256);
   hipLaunchKernelGGL((init_kernel<T>), grid, block, 0, s, a);
@@ -365,7 +388,7 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
   dugks_plan* P = new (std::nothrow) dugks_plan();
   if (!P) return DUGKS_ENOMEM;
   P->p = *p;
-  P->L = make_layout(p->nx, p->ny, p->precision);
+  P->L = make_layout(p->nx, p->ny, p->precision, p->scheme);
   P->dt = p->cfl;                 // Eq. (39), dx = sqrt(3RT) = 1
   P->h = 0.5 * P->dt;
   P->tau = p->mobility / RT;      // M_phi = tau RT
@@ -379,10 +402,54 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
   P->alpha = 2 * tau / (2 * tau + h);          // Eq. (27)
   P->beta = h / (2 * tau + h);
   P->gamma = tau * h / (2 * tau + h);
-  make_coefficients(p->recon, h, P->coef);
+  // launch kinds: T2 (f~ in, half step h), T3S3 stage A (f^ in, dt/6), stage B
+  // (f~ at t + dt/3 in, 5 dt/12); the shift identity above gives cbar with
+  // a = the input's shift and b = half of the stage's half step
+  auto stage = [&](int k, double hs, double a_in, double kap, double wo1, double wo2,
+                   double toff, double troff, double jdt, int jfirst) {
+    dugks_plan::StageCoef& c = P->st[k];
+    c.h = hs;
+    c.cbar = (a_in + 0.5 * hs) / (tau + a_in);
+    c.kap = kap;
+    c.wo1 = wo1;
+    c.wo2 = wo2;
+    c.alpha = 2 * tau / (2 * tau + hs);
+    c.beta = hs / (2 * tau + hs);
+    c.gamma = tau * hs / (2 * tau + hs);
+    c.toff = toff;
+    c.troff = troff;
+    c.jdt = jdt;
+    c.jfirst = jfirst;
+  };
+  // T2: f~+ = fbar+ + kap (X - fbar+), kap = cbar / (3 (1 - cbar))
+  stage(STAGE_T2, h, 0.5 * dt, P->cB2 / (3.0 * (1.0 - P->cB2)), 1.0, 0.0, 0.0, -dt, dt, 1);
+  P->st[STAGE_T2].cbar = P->cB2;   // the same value, rounded as Eq. 23's 3h / (2 tau + dt)
+  {
+    // stage A: cbar = 4 dt / (12 tau + 3 dt) (Eq. 31); f~+ (Eq. 33) and f^n
+    // (Eq. 32) are fbar+ -/+ (cbar / (4 (1 - cbar))) (X - fbar+)
+    const double c1 = (0.25 * dt + dt / 12.0) / (tau + 0.25 * dt);
+    stage(STAGE_A, dt / 6.0, 0.25 * dt, c1 / (4.0 * (1.0 - c1)), 1.0 / 3.0, 3.0 / 7.0, 0.0, -dt,
+          dt, 1);
+    // stage B: cbar = 9 dt / (24 tau + 4 dt) (Eq. 34); (3/4) dt (Omega + S)(t')
+    // = (3/4) dt 6 / ((6 tau + dt)(1 - cbar)) (X' - fbar+) (Eq. 29)
+    const double c2 = (dt / 6.0 + 5.0 * dt / 24.0) / (tau + dt / 6.0);
+    stage(STAGE_B, 5.0 * dt / 12.0, dt / 6.0,
+          0.75 * dt * 6.0 / ((6.0 * tau + dt) * (1.0 - c2)), 4.0 / 7.0, 0.0, dt / 3.0, 0.0,
+          dt / 3.0, 0);
+  }
+  const bool t3 = p->scheme == DUGKS_T3S3;
+  make_coefficients(p->recon, t3 ? P->st[STAGE_A].h : h, P->coef);
   if (!make_compact(p->recon, P->coef, P->compact)) {
     delete P;
     return DUGKS_EINVAL;   // cannot happen for the schemes built in
+  }
+  if (t3) {
+    double coef2[2][9][NTAP];
+    make_coefficients(p->recon, P->st[STAGE_B].h, coef2);
+    if (!make_compact(p->recon, coef2, P->compact2)) {
+      delete P;
+      return DUGKS_EINVAL;
+    }
   }
   make_tables(P);
   P->nstrips = (p->nx + OWN - 1) / OWN;

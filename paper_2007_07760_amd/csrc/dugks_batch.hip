@@ -359,6 +359,7 @@ int dugks_batch_set(dugks_batch* batch, int32_t slot, const dugks_plan* plan, vo
   if (plan->p.precision != batch->precision || plan->p.recon != batch->recon ||
       ((plan->p.flags & DUGKS_FLAG_MASS_FIX) != 0) != batch->mfix)
     return DUGKS_EINVAL;
+  if (plan->p.scheme != DUGKS_T2) return DUGKS_EUNSUPPORTED;
   Slot& s = batch->slots[slot];
   s.plan = plan;
   s.state = state;

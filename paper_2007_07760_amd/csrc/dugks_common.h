@@ -124,8 +124,8 @@ struct Tiling {
   }
 };
 
-// [header 256 B][coef table][x tables][y tables][buffer A][buffer B][mass scratch]
-// [row-group mass partials]
+// [header 256 B][coef table][coef table 2][x tables][y tables][buffer A][buffer B]
+// [T3S3: mid buffer, Q buffer][mass scratch][row-group and strip mass partials]
 struct StateHeader {
   uint64_t magic;
   double mass0;        // FP64 total of phi0
@@ -153,13 +153,14 @@ constexpr int FIX_THREADS = 1024;   // threads of the block that reduces the gro
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)
   Tiling tl;
-  size_t off_coef, off_tabx, off_taby, off_buf[2], off_scratch, off_groups, off_strips, total;
+  size_t off_coef, off_coef2, off_tabx, off_taby, off_buf[2], off_mid, off_q;
+  size_t off_scratch, off_groups, off_strips, total;
   int ngroups;         // row groups per strip
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline Layout make_layout(int nx, int ny, int precision) {
+inline Layout make_layout(int nx, int ny, int precision, int scheme) {
   Layout L;
   L.esize = precision == DUGKS_F64 ? 8 : 4;
   const int64_t line = 128 / (int64_t)L.esize;
@@ -171,12 +172,21 @@ inline Layout make_layout(int nx, int ny, int precision) {
   size_t off = sizeof(StateHeader);
   L.off_coef = off;
   off = align_up(off + NCOMPACT * L.esize, 256);
+  L.off_coef2 = off;
+  off = align_up(off + NCOMPACT * L.esize, 256);
   L.off_tabx = off;
   off = align_up(off + 2 * (2 * (size_t)nx + 2) * L.esize, 256);
   L.off_taby = off;
   off = align_up(off + 2 * (2 * (size_t)ny + 2) * L.esize, 256);
   for (int b = 0; b < 2; b++) {
     L.off_buf[b] = off;
+    off = align_up(off + buf_elems * L.esize, 256);
+  }
+  L.off_mid = L.off_q = 0;
+  if (scheme == DUGKS_T3S3) {
+    L.off_mid = off;
+    off = align_up(off + buf_elems * L.esize, 256);
+    L.off_q = off;
     off = align_up(off + buf_elems * L.esize, 256);
   }
   L.off_scratch = off;

@@ -31,15 +31,28 @@ struct StepArgs {
   int nx, ny;
   int seg_rows, nstrips, nsegs, nlogical;
   int ngroups;           // row groups of MASS_GROUP rows (mass partials)
-  T cB2;                 // fbar+ = f~ + cB2 (feq + tau S - f~)
-  T kap;                 // f~+ = fbar+ + kap (feq + tau S - fbar+)
+  T cB2;                 // fbar+ = g + cB2 (feq + tau S - g), g the stage's input
+  T kap;                 // output = base + kap (feq + tau S - fbar+) + wo1 dt L
+  T wo1, wo2;            // weights of dt L in the outputs (see Stage)
   T pscale;              // beta / alpha (the stencil table carries dt*alpha)
   T gdt;                 // dt * gamma / 2 (face S is the mean of two cells)
   T dt, tau, kth;        // kth = 4/W (0: theta off)
+  T jinv;                // 1 / (time between the two phi of d(phi u)/dt)
   double period;  // time modulation cos(pi t / period); 0 = steady
-  double dtd, hd; // dt, h in FP64 for the time factors
+  double dtd, hd; // dt; the stage's half step (faces at base time + hd)
+  double toff;    // base time of the stage: n dt + toff
+  double troff;   // time of the earlier phi of d(phi u)/dt: n dt + troff
   int jzero;      // 1: d(phi u)/dt = 0 on every step
+  int jfirst;     // 1: d(phi u)/dt = 0 on step 0 (no earlier phi yet)
 };
+
+// The launches of one time step.  T2: f~^n -> f~^{n+1} (Sec. II.B.1).  T3S3
+// (Sec. II.B.2) runs two: stage A reads f^^n, builds fbar+ with the half step
+// dt/6 (Eq. 31) and writes f~ at t_n + dt/3 (Eqs. 15, 33) and
+// Q = f^n + (3/7) dt L(f*) (Eq. 32 and the first flux term of Eq. 16); stage B
+// reads f~ at t_n + dt/3, builds fbar+ with the half step 5 dt/12 (Eq. 34) and
+// writes f^^{n+1} = Q + (3/4) dt (Omega + S) + (4/7) dt L(f**) (Eqs. 16, 29).
+enum Stage { STAGE_T2 = 0, STAGE_A = 1, STAGE_B = 2 };
 
 template <typename T>
 struct StepBufs {
@@ -132,13 +145,15 @@ __device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
   x[4] = P2 + dmp; x[8] = P2 - dmp;
 }
 
-template <typename T, int R, bool MFIX>
+template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
 
   const StepArgs<T>& a;
   const T* __restrict__ src;
   T* __restrict__ dst;
+  T* __restrict__ dst2;     // stage A: Q
+  const T* __restrict__ aux;  // stage B: Q
   cptr<T> cf;
   const T* __restrict__ tabx;
   cptr<T> taby;
@@ -328,25 +343,52 @@ struct Marcher {
     // f~+ and fbar+ both relax f~ towards X = feq + tau S (Eqs. 9, 23), so
     // f~+ = fbar+ + kap (X - fbar+): X of row k is rebuilt from its phi and m
     // (held since its cell stage) instead of reading f~ of the row again.
-    // Then f~^{n+1} = f~+ + dt L (Eq. 21).
+    // Then f~^{n+1} = f~+ + dt L (Eq. 21).  The T3S3 stages write their
+    // outputs in the same form (see Stage).
     double cs = 0.0, cf0 = 0.0;
     if (owned) {
       T x[9];
       collision_target(cp0, cx0, cy0, x);
       // the new row is not read again by this launch: stream it past the caches
       T* o = dst + (int64_t)kk * a.CH + loff;
+      if (STAGE == STAGE_T2) {
 #pragma unroll
-      for (int i = 0; i < 9; i++) {
-        const T bp = bfp[slotB(k)][i][L];
-        const T tfp = fma(a.kap, x[i] - bp, bp);
-        const T v = tfp + out[i];
-        __builtin_nontemporal_store(v, o + i * OWN);
-        if (MFIX) {
-          cs += (double)v;
-          if (i == 0 && v < T(MASS_FIT_MAX)) cf0 = 1.0;
+        for (int i = 0; i < 9; i++) {
+          const T bp = bfp[slotB(k)][i][L];
+          const T tfp = fma(a.kap, x[i] - bp, bp);
+          const T v = tfp + out[i];
+          __builtin_nontemporal_store(v, o + i * OWN);
+          if (MFIX) {
+            cs += (double)v;
+            if (i == 0 && v < T(MASS_FIT_MAX)) cf0 = 1.0;
+          }
         }
+        __builtin_nontemporal_store(ph0, o + 9 * OWN);
+      } else if (STAGE == STAGE_A) {
+        // f~(t') = f~+ + (1/3) dt L* and Q = f^n + (3/7) dt L*, with
+        // f~+ = fbar+ + kap (X - fbar+) and f^n = fbar+ - kap (X - fbar+)
+        T* o2 = dst2 + (int64_t)kk * a.CH + loff;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+          const T bp = bfp[slotB(k)][i][L];
+          const T d = x[i] - bp;
+          __builtin_nontemporal_store(fma(a.wo1, out[i], fma(a.kap, d, bp)), o + i * OWN);
+          __builtin_nontemporal_store(fma(a.wo2, out[i], fma(-a.kap, d, bp)), o2 + i * OWN);
+        }
+        __builtin_nontemporal_store(ph0, o + 9 * OWN);
+        __builtin_nontemporal_store(ph0, o2 + 9 * OWN);
+      } else {
+        // f^^{n+1} = Q + kap (X' - fbar+) + (4/7) dt L**, kap (X' - fbar+)
+        // being (3/4) dt (Omega + S) at t'; phi^n goes on as the history
+        const T* q = aux + (int64_t)kk * a.CH + loff;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+          const T bp = bfp[slotB(k)][i][L];
+          __builtin_nontemporal_store(fma(a.wo1, out[i], fma(a.kap, x[i] - bp, q[i * OWN])),
+                                      o + i * OWN);
+        }
+        __builtin_nontemporal_store(q[9 * OWN], o + 9 * OWN);
       }
-      __builtin_nontemporal_store(ph0, o + 9 * OWN);
     }
     if (MFIX) {
       // phi^{n+1} of the row into the group total; a group never straddles
@@ -408,16 +450,18 @@ struct Marcher {
 // One tile: the strip `strip` of the grid, rows of segment `seg`, step n.
 // pend = per-cell mass correction delta still to apply to the stored f~ of the
 // cells whose stored f~_0 is below fitmax (MFIX).
-template <typename T, int R, bool MFIX>
+template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
 __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
                                            const T* __restrict__ src, T* __restrict__ dst,
+                                           T* __restrict__ dst2, const T* __restrict__ aux,
                                            const T* __restrict__ cf,
                                            const T* __restrict__ tabx,
                                            const T* __restrict__ taby,
                                            double* __restrict__ part, double pend,
                                            double fitmax, int strip,
                                            int seg, T (*s_bfp)[9][LROW]) {
-  Marcher<T, R, MFIX> m{a, src, dst, as_const(cf), tabx, as_const(taby), s_bfp};
+  Marcher<T, R, MFIX, STAGE> m{a, src, dst, dst2, aux, as_const(cf), tabx, as_const(taby),
+                               s_bfp};
   const int lane = threadIdx.x;
   const int x0 = strip * OWN;
   m.lane = lane;
@@ -437,18 +481,20 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   m.VXc = tabx[(2 * a.nx + 2) + 2 * m.col + 1];
   m.UXe = tabx[2 * ce];
   m.VXe = tabx[(2 * a.nx + 2) + 2 * ce];
-  // time factors of the velocity at t_n, t_{n-1} (cells) and t_n + h (faces)
+  // time factors of the velocity at the stage's base time and at the time of
+  // the earlier phi (cells), and at base + its half step (faces)
   const double tn = (double)n * a.dtd;
+  const double tb = tn + a.toff;
   double gn = 1.0, gp = 1.0, gh = 1.0;
   if (a.period > 0.0) {
-    gn = cos(M_PI * tn / a.period);
-    gp = cos(M_PI * (tn - a.dtd) / a.period);
-    gh = cos(M_PI * (tn + a.hd) / a.period);
+    gn = cos(M_PI * tb / a.period);
+    gp = cos(M_PI * (tn + a.troff) / a.period);
+    gh = cos(M_PI * (tb + a.hd) / a.period);
   }
   m.gN = T(gn);
   m.gP = T(gp);
   m.gH = T(gh);
-  m.jscale = (n == 0 || a.jzero) ? T(0) : T(1) / a.dt;
+  m.jscale = ((n == 0 && a.jfirst) || a.jzero) ? T(0) : a.jinv;
   if (MFIX) {
     m.cw0 = T(wq(0) * pend);
     m.cw1 = T(wq(1) * pend);
@@ -459,12 +505,13 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   m.run();
 }
 
-template <typename T, int R, bool MFIX>
-__global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void step_kernel(
-    StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
-    const T* __restrict__ cf, const T* __restrict__ tabx, const T* __restrict__ taby,
-    double* __restrict__ part, const StateHeader* __restrict__ hdr) {
-  constexpr int RB = Marcher<T, R, MFIX>::RB;
+template <typename T, int R, bool MFIX, int STAGE>
+__global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void
+step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
+            T* __restrict__ dst2, const T* __restrict__ aux, const T* __restrict__ cf,
+            const T* __restrict__ tabx, const T* __restrict__ taby, double* __restrict__ part,
+            const StateHeader* __restrict__ hdr) {
+  constexpr int RB = Marcher<T, R, MFIX, STAGE>::RB;
   __shared__ T s_bfp[RB][9][LROW];
 
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
@@ -480,8 +527,8 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void step_ke
   __syncthreads();
   const double pend = MFIX ? hdr->pending : 0.0;
   const double fitmax = MFIX ? hdr->fit_max : 0.0;
-  march_tile<T, R, MFIX>(a, n, src, dst, cf, tabx, taby, part, pend, fitmax, strip, seg,
-                         s_bfp);
+  march_tile<T, R, MFIX, STAGE>(a, n, src, dst, dst2, aux, cf, tabx, taby, part, pend, fitmax,
+                                strip, seg, s_bfp);
 }
 
 // Neumaier pair (sum, compensation)
@@ -663,8 +710,8 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
     const int b = (int)(n & 1);
     const double pend = MFIX ? d->hdr->pending : 0.0;
     const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
-    march_tile<T, R, MFIX>(a, n, d->buf[b], d->buf[b ^ 1], d->cf, d->tabx, d->taby, d->part,
-                           pend, fitmax, strip, seg, s_bfp);
+    march_tile<T, R, MFIX>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf, d->tabx,
+                           d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
     // the next item's ring starts from its own rows; order this tile's LDS
     // reads before them
     wave_sync();
@@ -697,7 +744,7 @@ struct InitArgs {
   const T* __restrict__ tabx;
   const T* __restrict__ taby;
   Tiling tl;
-  double dt, kth;
+  double shift, kth;   // stored = feq - shift S (dt/2: f~ of T2, dt/4: f^ of T3S3)
 };
 
 // f~^0 = feq(phi0, u(x,0)) - (dt/2) S^0 with d(phi u)/dt = 0
@@ -728,7 +775,7 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
     const double en = ex(i) * nvx + ey(i) * nvy;
     const double feq = wq(i) * pC * (1.0 + 3.0 * eu);
     const double src = wq(i) * th * en;
-    a.buf[a.tl.idx(i, y, x)] = T(feq - 0.5 * a.dt * src);
+    a.buf[a.tl.idx(i, y, x)] = T(feq - a.shift * src);
   }
   a.buf[a.tl.idx(9, y, x)] = T(pC);
 }

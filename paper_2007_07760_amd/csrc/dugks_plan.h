@@ -16,6 +16,15 @@ struct dugks_plan {
   double dt, h, tau;
   double cA, cB, cA2, cB2, alpha, beta, gamma;
   double period;             // cos(pi t / period) modulation; 0 = steady
+  // coefficients of each launch kind (dugks::Stage): the face stencil is built
+  // with the stage's half step h; fbar+ = g + cbar (X - g) from the stage's
+  // input g; the outputs take kap (X - fbar+) and wo1 / wo2 dt L; d(phi u)/dt
+  // uses phi at n dt + toff and at n dt + troff
+  struct StageCoef {
+    double h, cbar, kap, wo1, wo2, alpha, beta, gamma, toff, troff, jdt;
+    int jfirst;
+  } st[3];
+  double compact2[dugks::NCOMPACT];  // T3S3 stage B stencil (compact: stage A)
   int seg_rows, nstrips, nsegs;
   std::vector<double> tabx, taby;
   // the constant head of every state of this plan (header, coefficient and
@@ -56,7 +65,7 @@ inline StepBufs<T> step_bufs(const dugks_plan* P, void* state, int64_t n) {
 }
 
 template <typename T>
-inline StepArgs<T> step_args(const dugks_plan* P) {
+inline StepArgs<T> step_args(const dugks_plan* P, int stage = STAGE_T2) {
   const Layout& L = P->L;
   StepArgs<T> a;
   a.CH = L.tl.CH;
@@ -67,16 +76,23 @@ inline StepArgs<T> step_args(const dugks_plan* P) {
   a.nsegs = P->nsegs;
   a.nlogical = P->nstrips * P->nsegs;
   a.ngroups = L.ngroups;
-  a.cB2 = T(P->cB2);
-  a.kap = T(P->cB2 / (3.0 * (1.0 - P->cB2)));
-  a.pscale = T(P->beta / P->alpha);
-  a.gdt = T(0.5 * P->dt * P->gamma);
+  const dugks_plan::StageCoef& c = P->st[stage];
+  a.cB2 = T(c.cbar);
+  a.kap = T(c.kap);
+  a.wo1 = T(c.wo1);
+  a.wo2 = T(c.wo2);
+  a.pscale = T(c.beta / c.alpha);
+  a.gdt = T(0.5 * P->dt * c.gamma);
   a.dt = T(P->dt);
+  a.jinv = T(1) / T(c.jdt);
+  a.toff = c.toff;
+  a.troff = c.troff;
+  a.jfirst = c.jfirst;
   a.tau = T(P->tau);
   a.kth = isfinite(P->p.width) ? T(4.0 / P->p.width) : T(0);
   a.period = P->period;
   a.dtd = P->dt;
-  a.hd = P->h;
+  a.hd = c.h;
   a.jzero = (P->p.flags & DUGKS_FLAG_DTPHIU_ZERO) ? 1 : 0;
   return a;
 }

@@ -2,10 +2,11 @@
 
 Each experiment is defined by the paper's dimensionless parameters (Pe = U0 L0 / M,
 Cn = W / L0, one period T_f = L0 / U0) and measured with the L2 error of Eq. 41
-between the final and the initial order parameter.  A whole table -- grids of
-different sizes, CFL numbers and periods -- runs as one FP64 batch (one
-persistent kernel per step over every grid; each grid stops at its own
-period).
+between the final and the initial order parameter.  For the T2 schemes a whole
+table -- grids of different sizes, CFL numbers and periods -- runs as one FP64
+batch (one persistent kernel per step over every grid; each grid stops at its
+own period); T3S3 entries run one grid at a time, and those with dt >= 12 tau,
+which the scheme does not allow, are left out as in the paper.
 
   translation  Sec. III.A: circle R = L0/5 at the centre, u = (U0, U0), one
                period T_f (Tables I-III).
@@ -21,6 +22,7 @@ period).
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -32,11 +34,12 @@ from .batch import Batch
 from .solver import Solver
 
 
-def translation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+def translation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int,
+                scheme: int = C.T2) -> dict:
     u0 = pe * m / n
     tf = n / u0
     return dict(kind="translation", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl,
-                recon=recon, vel_kind=C.VEL_UNIFORM, vel_param=(u0, u0),
+                recon=recon, scheme=scheme, vel_kind=C.VEL_UNIFORM, vel_param=(u0, u0),
                 steps=int(round(tf / cfl)),
                 phi0=lambda: I.tanh_circle(n, n, n / 2, n / 2, n / 5, cn * n))
 
@@ -44,10 +47,12 @@ def translation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) 
 ZALESAK_SLOT_DEPTH = 0.5   # of L0, from the bottom of the disk (not given)
 
 
-def zalesak(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+def zalesak(n: int, pe: float, cn: float, m: float, cfl: float, recon: int,
+            scheme: int = C.T2) -> dict:
     u0 = pe * m / n
     omega = u0 * math.pi / n
     return dict(kind="zalesak", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl, recon=recon,
+                scheme=scheme,
                 vel_kind=C.VEL_ROTATION, vel_param=(omega, n / 2, n / 2),
                 steps=int(round(2 * n / u0 / cfl)),
                 phi0=lambda: I.slotted_disk(n, n, n / 2, n / 2, 0.4 * n, 0.08 * n,
@@ -57,11 +62,12 @@ def zalesak(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> d
 DEFORMATION_RADIUS = 0.2   # of L0 (not given)
 
 
-def deformation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int) -> dict:
+def deformation(n: int, pe: float, cn: float, m: float, cfl: float, recon: int,
+                scheme: int = C.T2) -> dict:
     u0 = pe * m / n
     tf = n / u0
     return dict(kind="deformation", nx=n, ny=n, mobility=m, width=cn * n, cfl=cfl,
-                recon=recon, vel_kind=C.VEL_DEFORMATION, vel_param=(u0, tf),
+                recon=recon, scheme=scheme, vel_kind=C.VEL_DEFORMATION, vel_param=(u0, tf),
                 steps=int(round(tf / cfl)),
                 phi0=lambda: I.tanh_circle(n, n, n / 2, n / 2, DEFORMATION_RADIUS * n, cn * n))
 
@@ -72,12 +78,44 @@ def e_phi(phi: np.ndarray, phi0: np.ndarray) -> float:
     return float(np.sqrt(np.sum(d * d) / np.sum(phi0 * phi0)))
 
 
-def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float]:
-    """Run every configuration (one reconstruction) in one FP64 batch and
-    return E_phi of each after its own step count.  flags: plan flags
-    (DUGKS_FLAG_DTPHIU_ZERO drops d(phi u)/dt from the source)."""
+def allowed(c: dict) -> bool:
+    """T3S3 needs dt < 12 tau (tau = 3 M)."""
+    return c.get("scheme", C.T2) != C.T3S3 or c["cfl"] < 12.0 * 3.0 * c["mobility"]
+
+
+def _e_final(c: dict, phi: np.ndarray, phi0: np.ndarray) -> float:
+    if c["kind"] == "zalesak":
+        phi = (phi >= 0.5).astype(np.float64)   # step function of Sec. III.B
+    return e_phi(phi, phi0)
+
+
+def run_alone(configs: list[dict], flags: int = 0) -> list[float | None]:
+    """Each configuration on its own (per-step launches); None where the
+    scheme does not allow it."""
+    out = []
+    for c in configs:
+        if not allowed(c):
+            out.append(None)
+            continue
+        phi0 = c["phi0"]()
+        s = Solver(c["nx"], c["ny"], c["mobility"], c["width"], c["cfl"], recon=c["recon"],
+                   precision=C.F64, vel_kind=c["vel_kind"], vel_param=c["vel_param"],
+                   flags=flags, scheme=c.get("scheme", C.T2)).init(phi0)
+        s.step(c["steps"])
+        out.append(_e_final(c, s.phi().cpu().numpy(), phi0))
+        del s
+    return out
+
+
+def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float | None]:
+    """Run every configuration (one reconstruction) and return E_phi of each
+    after its own step count: T2 configurations in one FP64 batch, T3S3 ones
+    alone.  flags: plan flags (DUGKS_FLAG_DTPHIU_ZERO drops d(phi u)/dt from
+    the source)."""
     if not configs:
         return []
+    if any(c.get("scheme", C.T2) != C.T2 for c in configs):
+        return run_alone(configs, flags)
     recon = configs[0]["recon"]
     assert all(c["recon"] == recon for c in configs)
     b = Batch(len(configs), C.F64, recon, 0)
@@ -100,10 +138,7 @@ def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[floa
     assert all(int(st[k, 0]) == c["steps"] for k, c in enumerate(configs))
     out = []
     for s, c, phi0 in zip(sol, configs, p0):
-        phi = s.phi().cpu().numpy()
-        if c["kind"] == "zalesak":
-            phi = (phi >= 0.5).astype(np.float64)   # step function of Sec. III.B
-        out.append(e_phi(phi, phi0))
+        out.append(_e_final(c, s.phi().cpu().numpy(), phi0))
     del b, sol
     torch.cuda.empty_cache()
     return out
@@ -111,12 +146,20 @@ def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[floa
 
 # ---------------------------------------------------------------- the tables
 CFLS = (0.25, 0.5, 0.8)
-SCHEMES = {"T2S2CD": C.CENTRAL2, "T2S3": C.UPWIND3}
+# the paper's DUGKS variants: (face reconstruction, time discretisation)
+SCHEMES = {"T2S2CD": (C.CENTRAL2, C.T2), "T2S3": (C.UPWIND3, C.T2),
+           "T3S3": (C.UPWIND3, C.T3S3)}
 
 
 def table_configs(table: str, scheme: str) -> tuple[list, list[dict]]:
     """(column keys, configs in row-major order CFL x column) of a table."""
-    r = SCHEMES[scheme]
+    rec, sch = SCHEMES[scheme]
+    return _table(table, rec, functools.partial(translation, scheme=sch),
+                  functools.partial(zalesak, scheme=sch),
+                  functools.partial(deformation, scheme=sch))
+
+
+def _table(table, r, translation, zalesak, deformation):
     if table == "I":      # translation, N sweep, Pe = 128, Cn = 1/32, M = 0.02
         cols = [128, 192, 256, 384, 512]
         return cols, [translation(n, 128, 1 / 32, 0.02, c, r) for c in CFLS for n in cols]

@@ -17,11 +17,11 @@ class Solver:
 
     def __init__(self, nx, ny, mobility, width, cfl, recon=C.UPWIND3,
                  precision=C.F64, vel_kind=C.VEL_UNIFORM, vel_param=(0.0, 0.0),
-                 flags=0, tile_rows=0, device="cuda", state=None):
+                 flags=0, tile_rows=0, device="cuda", state=None, scheme=0):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (no CPU path exists)")
         self.params = C.make_params(nx, ny, mobility, width, cfl, recon, precision,
-                                    vel_kind, vel_param, flags, tile_rows)
+                                    vel_kind, vel_param, flags, tile_rows, scheme)
         self.nx, self.ny = int(nx), int(ny)
         self.precision = int(precision)
         self.dtype = torch.float64 if precision == C.F64 else torch.float32

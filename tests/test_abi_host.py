@@ -36,7 +36,8 @@ def _p(**kw):
     base.update(kw)
     flags = base.pop("flags", 0)
     tile = base.pop("tile_rows", 0)
-    return C.make_params(flags=flags, tile_rows=tile, **base)
+    scheme = base.pop("scheme", 0)
+    return C.make_params(flags=flags, tile_rows=tile, scheme=scheme, **base)
 
 
 @pytest.mark.parametrize("recon", [C.CENTRAL2, C.UPWIND3, C.CENTRAL4])
@@ -178,3 +179,21 @@ def test_device_circle_matches_host_circle(periodic):
     a = I.tanh_circle_torch(70, 50, 20.3, 31.7, 11.0, 4.0, periodic, "cpu").numpy()
     b = I.tanh_circle(70, 50, 20.3, 31.7, 11.0, 4.0, periodic=periodic)
     assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_plan_t3s3_validation(lib):
+    # dt < 12 tau: M = 0.02 -> tau = 0.06, 12 tau = 0.72
+    assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.5, scheme=1)) == C.OK
+    assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.73, scheme=1)) == C.EINVAL
+    assert C.dugks_plan_create_status(_p(mobility=0.01, cfl=0.5, scheme=1)) == C.EINVAL
+    assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.5, scheme=2)) == C.EINVAL
+    assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.5, scheme=1,
+                                         flags=C.FLAG_MASS_FIX)) == C.EUNSUPPORTED
+    a = C.dugks_plan_create(_p(mobility=0.02, cfl=0.5))
+    b = C.dugks_plan_create(_p(mobility=0.02, cfl=0.5, scheme=1))
+    try:
+        # T3S3 keeps two more buffers (f~ at t + dt/3 and Q) in its state
+        assert C.dugks_state_bytes(b) > C.dugks_state_bytes(a) + 1.9 * 10 * 64 * 48 * 8
+    finally:
+        C.dugks_plan_destroy(a)
+        C.dugks_plan_destroy(b)

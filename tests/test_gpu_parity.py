@@ -65,12 +65,13 @@ class _Twin:
 
 
 def _pair(gpu, orc, nx, ny, M, W, cfl, recon, kind, prm, phi0, tile_rows=0,
-          precision=0, flags=0, twin=True):
+          precision=0, flags=0, twin=True, scheme=0):
     print(f"case nx={nx} ny={ny} recon={recon} vel={kind} prm={prm} tile={tile_rows} "
-          f"prec={precision}", flush=True)
+          f"prec={precision} scheme={scheme}", flush=True)
     g = gpu(nx, ny, M, W, cfl, recon=recon, precision=precision, vel_kind=kind,
-            vel_param=prm, flags=flags, tile_rows=tile_rows).init(phi0)
-    p = orc.Params(nx, ny, M, W, cfl, recon, kind, prm, dtphiu_zero=bool(flags & 1))
+            vel_param=prm, flags=flags, tile_rows=tile_rows, scheme=scheme).init(phi0)
+    p = orc.Params(nx, ny, M, W, cfl, recon, kind, prm, dtphiu_zero=bool(flags & 1),
+                   scheme=scheme)
     return g, _Twin(orc, p, phi0, twin)
 
 

@@ -1,0 +1,103 @@
+"""DUGKS-T3S3 (Sec. II.B.2) on the GPU against the FP64 oracle.
+
+The library runs each T3S3 step as two launches of the march kernel (faces
+at t + dt/6 from fbar+ at t, and at t + 3 dt/4 from fbar+ at t + dt/3); the
+oracle takes the paper's steps (i)-(iv) one full-grid pass at a time.  Same
+bar as the T2 parity tests: FP64 relative L-inf <= max(1e-12, 100 x the
+divergence of the FMA-contracted twin of the oracle).
+"""
+import numpy as np
+import pytest
+
+from paper_2007_07760_amd import inputs as I
+from test_gpu_parity import KINDS, TOL64, _check, _pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2007_07760_amd import _lib
+    _lib.load()
+    from paper_2007_07760_amd.solver import Solver
+    return Solver
+
+
+@pytest.mark.parametrize("recon", [0, 1, 2])
+@pytest.mark.parametrize("kind", range(4))
+def test_t3s3_ragged_all_schemes(gpu, orc, recon, kind):
+    """100 x 72 (two strips, ragged), every reconstruction and velocity kind;
+    M = 0.02, C = 0.6 (dt < 12 tau = 0.72)."""
+    nx, ny = 100, 72
+    phi0 = I.random_circles(nx, ny, 5, 6.0, 14.0, 4.0, seed=21 + kind)
+    k, prm = KINDS[kind]
+    g, o = _pair(gpu, orc, nx, ny, 0.02, 4.0, 0.6, recon, k, prm, phi0, tile_rows=16,
+                 scheme=1)
+    for steps in (1, 2, 23):
+        g.step(steps)
+        o.run(steps)
+        _check(g, o, f"t3s3 ragged +{steps}")
+
+
+@pytest.mark.parametrize("shape,tile", [((8, 8), 1), ((59, 13), 5), ((130, 11), 64)])
+def test_t3s3_edge_sizes(gpu, orc, shape, tile):
+    nx, ny = shape
+    phi0 = I.random_smooth(nx, ny, seed=nx * 5 + ny)
+    for recon in (0, 1, 2):
+        g, o = _pair(gpu, orc, nx, ny, 0.04, 3.0, 0.8, recon, 0, (0.02, 0.03), phi0,
+                     tile_rows=tile, scheme=1)
+        g.step(10)
+        o.run(10)
+        _check(g, o, f"t3s3 edge recon {recon}")
+
+
+def test_t3s3_tile_shape_invariance_bitwise(gpu):
+    nx, ny = 150, 97
+    phi0 = I.random_circles(nx, ny, 6, 6.0, 20.0, 4.0, seed=4)
+    for precision in (0, 1):
+        ref = None
+        for tile in (0, 1, 16, 33):
+            g = gpu(nx, ny, 0.02, 4.0, 0.5, recon=1, precision=precision, vel_kind=2,
+                    vel_param=(0.05, 400.0), tile_rows=tile, scheme=1).init(phi0)
+            g.step(15)
+            f = g.distributions().cpu().numpy()
+            if ref is None:
+                ref = f
+            else:
+                assert np.array_equal(f, ref), (precision, tile)
+
+
+def test_t3s3_mass_and_fp32(gpu):
+    """Mass is conserved in FP64; FP32 stays close to FP64 over 300 steps."""
+    w = I.workload("c2")
+    kw = dict(recon=1, vel_kind=w["vel_kind"], vel_param=w["vel_param"], scheme=1)
+    g64 = gpu(w["nx"], w["ny"], 0.02, w["width"], w["cfl"], **kw).init(w["phi0"])
+    g32 = gpu(w["nx"], w["ny"], 0.02, w["width"], w["cfl"], precision=1, **kw).init(w["phi0"])
+    m0 = g64.mass0()
+    g64.step(300)
+    g32.step(300)
+    drift = abs(g64.mass() - m0) / m0
+    d = np.max(np.abs(g32.phi().cpu().numpy() - g64.phi().cpu().numpy()))
+    print(f"t3s3 FP64 drift {drift:.2e}, FP32 vs FP64 phi L-inf {d:.2e}", flush=True)
+    assert drift < 1e-15 * 300
+    assert d < 1e-4
+
+
+def test_t3s3_rejects_large_step(gpu):
+    from paper_2007_07760_amd import _lib as C
+    with pytest.raises(C.DugksError):
+        gpu(64, 64, 0.01, 4.0, 0.5, recon=1, scheme=1)   # dt = 0.5 >= 12 tau = 0.36
+
+
+def test_t3s3_headline_size_two_steps(gpu, orc):
+    """4096^2, 64 circles in rotation, M = 0.02: the full field after two steps."""
+    w = I.workload("h1")
+    g, o = _pair(gpu, orc, w["nx"], w["ny"], 0.02, w["width"], w["cfl"], w["recon"],
+                 w["vel_kind"], w["vel_param"], w["phi0"], twin=False, scheme=1)
+    g.step(2)
+    o.run(2)
+    ef, ep, _ = _check(g, o, "t3s3 h1 step 2")
+    assert ef < TOL64 and ep < TOL64
