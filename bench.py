@@ -11,11 +11,16 @@ every step) is reported in the same line, and so are the batched form (256
 uneven grids, 32-512 per side, one persistent kernel, hipGraph replays of 50
 steps, autotuned tile height, against one launch per grid and step) and the
 serving form (a scaled request stream served by continuous batching, against
-one-at-a-time execution).
+one-at-a-time execution), and the three-level DUGKS-T3S3 step (two fused
+stage kernels per step) on the same field with M = 0.02, since T3S3 needs
+dt < 12 tau = 36 M.
 
 MLUPS = nx * ny * steps / time / 1e6.  Algorithmic traffic per lattice update:
 f~^n in and f~^{n+1} out (9 + 9 words), phi^{n-1} in and phi^n out (2 words):
-160 B in FP64, 80 B in FP32.  Peak HBM bandwidth of MI355X: 8 TB/s.
+160 B in FP64, 80 B in FP32.  T3S3: stage A reads f^^n and phi^{n-1} (10
+words) and writes f~(t') and Q with the phi plane (20), stage B reads both
+(20) and writes f^^{n+1} (10): 60 words, 480 B in FP64.  Peak HBM bandwidth of
+MI355X: 8 TB/s.
 """
 from __future__ import annotations
 
@@ -27,7 +32,9 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_LU = 20
-CPU_STEPS = 8          # oracle sample: about 10-30 s on the host cores
+WORDS_PER_LU_T3S3 = 60
+T3S3_MOBILITY = 0.02
+CPU_STEPS = 16         # oracle sample: about 10-30 s on the host cores
 
 
 def parse():
@@ -43,6 +50,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--only-batch", action="store_true",
                     help="the batched section alone (profiling runs)")
+    ap.add_argument("--no-t3s3", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one precision only (profiling runs)")
@@ -110,11 +118,10 @@ def copy_bandwidth():
     return gbs
 
 
-def profile_traffic(kernel_prefix: str, precision: str):
-    """HBM bytes per launch of the step kernel from a committed rocprofv3 PMC
-    summary (profiles/traffic_<precision>.json), if it matches this build."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        f"traffic_h1_{precision}.json")
+def _profile_record(name: str):
+    """A committed rocprofv3 PMC summary (profiles/<name>.json) if it was taken
+    with the kernel sources of this build, else None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     try:
@@ -122,9 +129,46 @@ def profile_traffic(kernel_prefix: str, precision: str):
         from paper_2007_07760_amd import kernel_fingerprint
         if rec.get("kernel_fingerprint") != kernel_fingerprint():
             return None
-        return rec.get("bytes_per_launch")
+        return rec
     except Exception:
         return None
+
+
+def profile_traffic(precision: str):
+    """HBM bytes per launch of the T2 step kernel (profiles/traffic_h1_<precision>.json)."""
+    rec = _profile_record(f"traffic_h1_{precision}")
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def profile_traffic_t3s3():
+    """HBM bytes of one T3S3 step (stage A + stage B launches)."""
+    rec = _profile_record("traffic_h1_t3s3_f64")
+    if not rec:
+        return None
+    return rec["stage_a"]["bytes_per_launch"] + rec["stage_b"]["bytes_per_launch"]
+
+
+def bench_t3s3(w, steps, warmup):
+    """The DUGKS-T3S3 step (stage A + stage B kernels) on the headline field
+    with M = T3S3_MOBILITY, FP64."""
+    import torch
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd.solver import Solver
+    s = Solver(w["nx"], w["ny"], T3S3_MOBILITY, w["width"], w["cfl"], recon=w["recon"],
+               precision=C.F64, vel_kind=w["vel_kind"], vel_param=w["vel_param"],
+               scheme=C.T3S3).init(w["phi0"])
+    wall, ev_ms = time_steps(s, steps, warmup)
+    k_ms = time_kernel_only(s, min(steps, 50))
+    lus = w["nx"] * w["ny"]
+    achieved = WORDS_PER_LU_T3S3 * 8 * lus / (k_ms * 1e-3) / 1e9
+    del s
+    torch.cuda.empty_cache()
+    return {"value": round(lus * steps / (ev_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ev_ms / steps, 4), "dtype": "f64",
+            "mobility": T3S3_MOBILITY, "kernels": "step_kernel stage A + stage B",
+            "step_kernels_ms": round(k_ms, 4), "achieved": round(achieved, 1),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profile_traffic_t3s3(), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
 
 
 def bench_batched(steps):
@@ -278,7 +322,7 @@ def main():
         results[prec_name] = dict(
             wall=wall, ev_ms=ev_ms, kernel_ms=k_ms, achieved=achieved,
             mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6,
-            traffic=profile_traffic("step_kernel", prec_name))
+            traffic=profile_traffic(prec_name))
         del s
         torch.cuda.empty_cache()
     copy_gbs = copy_bandwidth()
@@ -320,6 +364,8 @@ def main():
                         "achieved": round(f["achieved"], 1),
                         "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
                         "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4}
+    if not args.no_t3s3 and not args.only:
+        line["t3s3"] = bench_t3s3(w, args.steps, args.warmup)
     if not args.no_batch and not args.only:
         line["batched"] = bench_batched(args.batch_steps)
     if not args.no_serve and not args.only:

@@ -1,8 +1,12 @@
 """Pins of the oracle's DUGKS-T3S3 step (Sec. II.B.2) against what the paper
 and the mathematics fix: exact mass conservation, constant states, periodic
-shifts (bitwise), mirror symmetry, and the paper's own Table I value for the
-diagonal translation at N = 128, C = 0.5 (slow).  The auxiliary-shift
-coefficients it uses (Eqs. 31-34) are pinned in test_oracle_pins."""
+shifts, mirror symmetry, the decay rate and phase of a Fourier mode of the
+linear advection-diffusion limit (which every coefficient of the two stages
+moves), the moments of the first state, and the paper's own Table I value
+for the diagonal translation at N = 128, C = 0.5 (slow).  The
+auxiliary-shift coefficients it uses (Eqs. 31-34) are pinned in
+test_oracle_pins."""
+import math
 import os
 
 import numpy as np
@@ -55,6 +59,57 @@ def test_t3s3_mirror_equivariance(orc):
     a = _state(orc, 32, 32, 0.02, 0.5, 1, 0, (0.03, 0.02), phi0).run(12)
     b = _state(orc, 32, 32, 0.02, 0.5, 1, 0, (-0.03, 0.02), phi0[:, ::-1].copy()).run(12)
     assert np.max(np.abs(a.phi()[:, ::-1] - b.phi())) < 1e-13
+
+
+@pytest.mark.parametrize("recon,vel,cfl", [(0, (0.1, 0.0), 0.5), (1, (0.07, 0.07), 0.8)])
+def test_t3s3_fourier_mode_decay_and_phase(orc, recon, vel, cfl):
+    """With theta off, Eq. (1) is linear advection-diffusion: a cosine mode
+    decays as exp(-M k^2 t) and moves with u.  The rate is within 6e-4 of
+    M k^2 here; each of these slips moves it by more than 6e-3: the 3/7 and
+    4/7 weights of Eq. 16 swapped, 3/4 dt of the collision part at t' made
+    dt/2, the factor of Eq. 29 read as 6 dt / (6 tau + dt), either stage's
+    face half step (dt/6, 5 dt/12) changed, d(phi u)/dt at t' dropped."""
+    nx, ny, M = 128, 8, 0.05
+    ux, uy = vel
+    amp, k = 0.1, 2 * math.pi / nx
+    phi0 = I.cosine_mode(nx, ny, amp, 1, 0)
+    p = orc.Params(nx, ny, M, math.inf, cfl, recon, 0, (ux, uy), scheme=orc.T3S3)
+    steps = int(round(1000 / cfl))
+    t = steps * cfl
+    phi = orc.State(p, phi0).run(steps).phi()
+    assert np.ptp(phi, axis=0).max() < 1e-13     # stays one-dimensional
+    x = np.arange(nx) + 0.5
+    A = 2.0 / nx * np.sum((phi[0] - 0.5) * np.exp(-1j * k * x))
+    rate = -math.log(abs(A) / amp) / t
+    assert rate == pytest.approx(M * k * k, rel=2e-3)
+    shift = (-np.angle(A)) % (2 * math.pi)
+    want = (k * ux * t) % (2 * math.pi)
+    assert abs(shift - want) < 1e-3 * k * ux * t
+
+
+EX = np.array([0, 1, 1, 0, -1, -1, -1, 0, 1], dtype=float)
+EY = np.array([0, 0, 1, 1, 1, 0, -1, -1, -1], dtype=float)
+
+
+def test_t3s3_first_state_moments(orc):
+    """The first state is f = f^eq (Omega = 0, d(phi u)/dt = 0): T2 stores
+    f~ = f^eq - (dt/2) S, T3S3 f^ = f^eq - (dt/4) S, so 2 f^ - f~ = f^eq, whose
+    moments are phi0 and phi0 u exactly (Eq. 14).  With theta on, S has a
+    first moment of its own, so a wrong offset of either state shows."""
+    nx, ny = 40, 36
+    phi0 = I.random_circles(nx, ny, 3, 4.0, 9.0, 4.0, seed=3)
+    u = (0.03, -0.02)
+    t2 = orc.State(orc.Params(nx, ny, 0.02, 4.0, 0.5, 1, 0, u), phi0).tf
+    t3 = orc.State(orc.Params(nx, ny, 0.02, 4.0, 0.5, 1, 0, u, scheme=orc.T3S3), phi0).tf
+    g = 2.0 * t3 - t2
+    assert np.max(np.abs(g.sum(axis=0) - phi0)) < 1e-15
+    mx = np.tensordot(EX, g, axes=1)
+    my = np.tensordot(EY, g, axes=1)
+    assert np.max(np.abs(mx - phi0 * u[0])) < 1e-16
+    assert np.max(np.abs(my - phi0 * u[1])) < 1e-16
+    # the source's own first moment is not small (the check has teeth)
+    s_x = np.tensordot(EX, t2 - t3, axes=1) / (-0.5 / 4)
+    assert np.max(np.abs(s_x)) > 1e-3
 
 
 @pytest.mark.slow
