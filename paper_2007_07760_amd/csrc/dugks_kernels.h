@@ -1,21 +1,27 @@
-// dugks_kernels.h -- device kernels of one D2Q9 DUGKS (T2) step for the
-// conservative Allen-Cahn equation (arXiv 2007.07760, Sec. II).
+// dugks_kernels.h -- device kernels of one D2Q9 DUGKS step for the
+// conservative Allen-Cahn equation (arXiv 2007.07760, Sec. II): the T2 step
+// and the two stages of the T3S3 step.
 //
 // The fused step kernel: one wavefront owns a strip of OWN = 58 columns (its 64
-// lanes carry 3 halo columns each side) and marches up a segment of rows.  Per
-// row it
-//   - loads the 9 f~ planes and the phi history of row r+1 (coalesced, x fastest),
-//   - forms phi (Eq. 30) into an LDS ring,
-//   - at row r: the isotropic normal, theta (Eqs. 2, 4), d(phi u)/dt, and from
-//     Eq. (14) feq and S collapsed into fbar+ (Eq. 23, LDS ring of 4-5 rows) and
-//     f~+ (Eq. 9, registers),
+// lanes carry 3 halo columns each side) and marches up a segment of rows.  At
+// row r it
+//   - sums phi (Eq. 30) of row r+1 (loaded one row earlier) and keeps phi and
+//     its horizontal differences in registers,
+//   - forms, at the cells of row r, the isotropic normal, theta (Eqs. 2, 4),
+//     d(phi u)/dt and from Eq. (14) feq and S, collapsed into X = feq + tau S
+//     and fbar+ (Eq. 23) -> an LDS ring of 4 rows (5 for central-4),
+//   - issues the loads of row r+2 (the 9 f~ planes and the phi history,
+//     coalesced, x fastest),
 //   - at row k = r-2: the face values fbar(x_b, t+h) of the east and north face
 //     of each cell (Eqs. 24-26, each a fixed stencil of <= 20 taps with
 //     coefficients built on the host), phi_b (Eq. 28), feq_b, S_b and f_b
-//     (Eq. 27), the meso-flux (Eq. 21) and the update f~^{n+1} = f~+ + dt L,
+//     (Eq. 27), the meso-flux (Eq. 21) and the update f~^{n+1} = f~+ + dt L
+//     with f~+ (Eq. 9) rebuilt from fbar+ and X,
 // and writes f~^{n+1} and phi^n of its own cells.  Neighbour columns come from
-// LDS, the own column's pipeline lives in registers; the loop is unrolled by 3
-// so the register ring rotates without moves.
+// LDS or DPP lane shifts; the own column's pipeline lives in registers.  The
+// first rows of a tile (no faces yet) are peeled off the loop, so that every
+// row of the loop issues the same loads and stores and the waits for the loads
+// never cover stores.
 #pragma once
 
 #include "dugks_common.h"
@@ -98,26 +104,52 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 }
 
 // Value of the lane to the right / left through the DPP wavefront shifts
-// (wave_shl:1 moves lane i+1 into lane i, wave_shr:1 lane i-1); the two edge
-// lanes keep their own value -- they are halo lanes whose results are never
-// stored.
+// (wave_shl:1 moves lane i+1 into lane i, wave_shr:1 lane i-1).  The edge
+// lane with no source (63 / 0) reads 0 (bound_ctrl), which makes each shift
+// one instruction.  Nothing of lanes 0 and 63 reaches an owned cell: the owned
+// lanes 3..60 read fbar+ of lanes 1..62 at most (central-4's tangential
+// differences), whose values depend on phi of lanes 0..63 only, and every
+// face a lane takes from a neighbour belongs to lanes 2..61.
 template <int CTRL>
 __device__ __forceinline__ float dpp_shift(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, CTRL, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v) {
   const long long b = __double_as_longlong(v);
-  int lo = (int)b, hi = (int)(b >> 32);
-  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 template <typename T>
 __device__ __forceinline__ T from_right(T v) { return dpp_shift<0x130>(v); }
 template <typename T>
 __device__ __forceinline__ T from_left(T v) { return dpp_shift<0x138>(v); }
+
+// Stores (and stage B's loads of Q) through a buffer resource: a lane whose
+// byte offset lies past the resource's size writes nothing / reads 0 (the
+// hardware range check), so a row's stores are issued by every lane on every
+// row and the wait counts of the loads that follow them are the same on every
+// path.  aux 2 = nontemporal.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned OFF_NONE = 0x80000000u;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 2);
+}
+__device__ __forceinline__ float bload(rsrc_t r, unsigned off, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(rsrc_t r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 2);
+}
 
 // Ordering point for LDS traffic inside the (single-wavefront) workgroup: a
 // wavefront's LDS operations execute in program order, so only the compiler
@@ -145,6 +177,18 @@ __device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
   x[4] = P2 + dmp; x[8] = P2 - dmp;
 }
 
+// num / max(|g|, 1e-12): FP64 rounds the square root and the quotient
+// exactly; FP32 multiplies by the hardware reciprocal square root (about
+// 1 ulp), which saves the ~25 instructions per row of an exact square root
+// and division
+__device__ __forceinline__ double over_norm(double num, double gx, double gy) {
+  const double gm = sqrt(fma(gx, gx, gy * gy));
+  return num / (gm > 1e-12 ? gm : 1e-12);
+}
+__device__ __forceinline__ float over_norm(float num, float gx, float gy) {
+  return num * __builtin_amdgcn_rsqf(fmaxf(fmaf(gx, gx, gy * gy), 1e-24f));
+}
+
 template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
@@ -159,6 +203,8 @@ struct Marcher {
   cptr<T> taby;
   T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
+  int ocol;                 // owned lanes: column within the strip
+  rsrc_t rdst, rdst2, rpart, raux;
   int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
   bool owned;
   int y0, y1, base;
@@ -224,9 +270,7 @@ struct Marcher {
     const T gx = fma(T(4), D1, D0 + D2) * twelfth;
     const T gy = (A2 - A0) * twelfth;
     const T pC = ph2;
-    const T gm = sqrt(fma(gx, gx, gy * gy));
-    const T den = gm > T(1e-12) ? gm : T(1e-12);
-    const T th = a.kth * pC * (T(1) - pC) / den;   // theta / |grad phi|
+    const T th = over_norm(a.kth * pC * (T(1) - pC), gx, gy);   // theta / |grad phi|
     const int rr = wrapi(r, a.ny);
     const T UYr = taby[2 * rr + 1];
     const T VYr = taby[(2 * a.ny + 2) + 2 * rr + 1];
@@ -270,10 +314,19 @@ struct Marcher {
   // P = beta phi_b, Q = 3 P u_b + gamma S_b/w-part, so the flux differences
   // split into a per-velocity part, accumulated as each fbar_i is formed, and
   // a collision part in the 3 numbers (P, Qx, Qy) of each face.
+  template <bool upd>
   __device__ __forceinline__ void face_stage(int k) {
     const int L = LPAD + lane;
-    const bool upd = k >= y0;
     const int kk = wrapi(k, a.ny);
+    // stage B: Q of the row (Eq. 32 value), read before the face work so that
+    // its loads are in flight meanwhile; lanes outside the owned columns read
+    // nothing (out-of-range offsets read 0)
+    T qv[10];
+    if (STAGE == STAGE_B && upd) {
+      const unsigned oq = owned ? (unsigned)((kk * a.CH + ocol) * (int)sizeof(T)) : OFF_NONE;
+#pragma unroll
+      for (int i = 0; i < 10; i++) qv[i] = bload(raux, oq + i * (unsigned)(OWN * sizeof(T)), T(0));
+    }
     T out[9];
     T phN = T(0), phE = T(0);
 #pragma unroll
@@ -346,48 +399,47 @@ struct Marcher {
     // Then f~^{n+1} = f~+ + dt L (Eq. 21).  The T3S3 stages write their
     // outputs in the same form (see Stage).
     double cs = 0.0, cf0 = 0.0;
-    if (owned) {
+    {
       T x[9];
       collision_target(cp0, cx0, cy0, x);
-      // the new row is not read again by this launch: stream it past the caches
-      T* o = dst + (int64_t)kk * a.CH + loff;
+      // the new row is not read again by this launch: stream it past the
+      // caches; lanes outside the owned columns store nothing
+      const unsigned ob = owned ? (unsigned)((kk * a.CH + ocol) * (int)sizeof(T)) : OFF_NONE;
+      constexpr unsigned PL = OWN * sizeof(T);
       if (STAGE == STAGE_T2) {
 #pragma unroll
         for (int i = 0; i < 9; i++) {
           const T bp = bfp[slotB(k)][i][L];
           const T tfp = fma(a.kap, x[i] - bp, bp);
           const T v = tfp + out[i];
-          __builtin_nontemporal_store(v, o + i * OWN);
+          bstore(v, rdst, ob + i * PL);
           if (MFIX) {
-            cs += (double)v;
-            if (i == 0 && v < T(MASS_FIT_MAX)) cf0 = 1.0;
+            cs += owned ? (double)v : 0.0;
+            if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
           }
         }
-        __builtin_nontemporal_store(ph0, o + 9 * OWN);
+        bstore(ph0, rdst, ob + 9 * PL);
       } else if (STAGE == STAGE_A) {
         // f~(t') = f~+ + (1/3) dt L* and Q = f^n + (3/7) dt L*, with
         // f~+ = fbar+ + kap (X - fbar+) and f^n = fbar+ - kap (X - fbar+)
-        T* o2 = dst2 + (int64_t)kk * a.CH + loff;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
           const T bp = bfp[slotB(k)][i][L];
           const T d = x[i] - bp;
-          __builtin_nontemporal_store(fma(a.wo1, out[i], fma(a.kap, d, bp)), o + i * OWN);
-          __builtin_nontemporal_store(fma(a.wo2, out[i], fma(-a.kap, d, bp)), o2 + i * OWN);
+          bstore(fma(a.wo1, out[i], fma(a.kap, d, bp)), rdst, ob + i * PL);
+          bstore(fma(a.wo2, out[i], fma(-a.kap, d, bp)), rdst2, ob + i * PL);
         }
-        __builtin_nontemporal_store(ph0, o + 9 * OWN);
-        __builtin_nontemporal_store(ph0, o2 + 9 * OWN);
+        bstore(ph0, rdst, ob + 9 * PL);
+        bstore(ph0, rdst2, ob + 9 * PL);
       } else {
         // f^^{n+1} = Q + kap (X' - fbar+) + (4/7) dt L**, kap (X' - fbar+)
         // being (3/4) dt (Omega + S) at t'; phi^n goes on as the history
-        const T* q = aux + (int64_t)kk * a.CH + loff;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
           const T bp = bfp[slotB(k)][i][L];
-          __builtin_nontemporal_store(fma(a.wo1, out[i], fma(a.kap, x[i] - bp, q[i * OWN])),
-                                      o + i * OWN);
+          bstore(fma(a.wo1, out[i], fma(a.kap, x[i] - bp, qv[i])), rdst, ob + i * PL);
         }
-        __builtin_nontemporal_store(q[9 * OWN], o + 9 * OWN);
+        bstore(qv[9], rdst, ob + 9 * PL);
       }
     }
     if (MFIX) {
@@ -396,32 +448,38 @@ struct Marcher {
       // fixed butterfly after rows in order -- does not depend on the tiling
       macc += cs;
       mcnt += cf0;
-      if ((k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1) {
-        double v = macc, w = mcnt;
+      const bool gend = (k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1;
+      double v = 0.0, w = 0.0;
+      if (gend) {
+        v = macc;
+        w = mcnt;
 #pragma unroll
         for (int m = 1; m < LANES; m <<= 1) {
           v += __shfl_xor(v, m);
           w += __shfl_xor(w, m);
         }
-        if (lane == 0) {
-          part_row[2 * (k / MASS_GROUP)] = v;
-          part_row[2 * (k / MASS_GROUP) + 1] = w;
-        }
         macc = 0.0;
         mcnt = 0.0;
       }
+      // issued on every row; only lane 0 at the end of a group writes
+      const unsigned po = (gend && lane == 0) ? (unsigned)(16 * (k / MASS_GROUP)) : OFF_NONE;
+      bstore(v, rpart, po);
+      bstore(w, rpart, po + 8);
     }
   }
 
-  // row r of the march: phi of r+1, cell terms of r, load r+2, faces of r-2
+  // row r of the march: phi of r+1, cell terms of r, load r+2 (the last rows
+  // load row y1 + 2 again, so that every row issues the same loads), faces
+  // of r-2 (none for the first rows of the tile; the north faces only for
+  // row y0 - 1, the south faces of row y0)
+  template <int FACE>
   __device__ __forceinline__ void body(int r, RowRegs<T>& cur, RowRegs<T>& nxt) {
-    if (r > y1 + 1) return;
     phi_push(nxt);
     cell_stage(cur, r);
-    if (r + 2 <= y1 + 2) load_row(cur, r + 2);
+    load_row(cur, min(r + 2, y1 + 2));
     wave_sync();
-    const int k = r - 2;
-    if (k >= y0 - 1) face_stage(k);
+    if (FACE == 1) face_stage<false>(r - 2);
+    if (FACE == 2) face_stage<true>(r - 2);
     wave_sync();
   }
 
@@ -440,10 +498,20 @@ struct Marcher {
     load_row(B, y0 - 2);
     phi_push(B);
     load_row(C, y0 - 1);
-    for (int r = y0 - 2; r <= y1 + 1; r += 2) {
-      body(r, B, C);
-      body(r + 1, C, B);
+    body<0>(y0 - 2, B, C);
+    body<0>(y0 - 1, C, B);
+    body<0>(y0, B, C);
+    body<1>(y0 + 1, C, B);
+    // the first full row before the loop, so that the loop is entered, as it
+    // is repeated, right after a full row's loads and stores: the waits for
+    // the loads at its head then never include stores
+    body<2>(y0 + 2, B, C);
+    int r = y0 + 3;
+    for (; r + 1 <= y1 + 1; r += 2) {
+      body<2>(r, C, B);
+      body<2>(r + 1, B, C);
     }
+    if (r <= y1 + 1) body<2>(r, C, B);
   }
 };
 
@@ -473,6 +541,15 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   }
   const int nown = min(OWN, a.nx - x0);
   m.owned = lane >= HALO && lane < HALO + nown;
+  m.ocol = lane - HALO;
+  {
+    // the strip's own chunk column: ny rows of CH elements
+    const int64_t c0 = (int64_t)strip * a.ny * a.CH;
+    const unsigned nb = (unsigned)((int64_t)a.ny * a.CH * (int64_t)sizeof(T));
+    m.rdst = make_rsrc(dst + c0, nb);
+    m.rdst2 = make_rsrc((STAGE == STAGE_A ? dst2 : dst) + c0, nb);
+    m.raux = make_rsrc((STAGE == STAGE_B ? aux : src) + c0, nb);   // used by stage B
+  }
   m.y0 = seg * a.seg_rows;
   m.y1 = min(m.y0 + a.seg_rows, a.ny);
   m.base = m.y0 - 3;
@@ -501,6 +578,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
     m.cw2 = T(wq(2) * pend);
     m.fitmax = T(fitmax);
     m.part_row = part + 2 * (int64_t)strip * a.ngroups;
+    m.rpart = make_rsrc(m.part_row, (unsigned)(16 * a.ngroups));
   }
   m.run();
 }

@@ -114,6 +114,17 @@ def test_c1_full_period(gpu, orc):
         ef, ep, tw = _check(g, o, f"c1 step {target}")
         if target <= 1600:
             assert ef < TOL64 and ep < TOL64
+        if target == 1600:
+            # half a period: u t = (32, 32) cells, so the exact answer is phi0
+            # rolled by 32 cells along both axes (Eq. 41 against it)
+            half = np.roll(w["phi0"], (32, 32), axis=(0, 1))
+            hg = orc.e_phi(g.phi().cpu().numpy(), half)
+            ho = orc.e_phi(o.phi(), half)
+            still = orc.e_phi(g.phi().cpu().numpy(), w["phi0"])
+            print(f"half period: E_phi vs rolled phi0 gpu {hg:.6e} oracle {ho:.6e}; "
+                  f"vs unmoved phi0 {still:.3e}", flush=True)
+            assert hg == pytest.approx(ho, rel=1e-9)
+            assert hg < 0.05 and still > 10 * hg
     eg = orc.e_phi(g.phi().cpu().numpy(), w["phi0"])
     eo = orc.e_phi(o.phi(), w["phi0"])
     print(f"E_phi gpu {eg:.6e} oracle {eo:.6e}", flush=True)
