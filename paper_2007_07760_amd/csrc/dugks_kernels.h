@@ -177,16 +177,13 @@ __device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
   x[4] = P2 + dmp; x[8] = P2 - dmp;
 }
 
-// num / max(|g|, 1e-12): FP64 rounds the square root and the quotient
-// exactly; FP32 multiplies by the hardware reciprocal square root (about
-// 1 ulp), which saves the ~25 instructions per row of an exact square root
-// and division
-__device__ __forceinline__ double over_norm(double num, double gx, double gy) {
-  const double gm = sqrt(fma(gx, gx, gy * gy));
-  return num / (gm > 1e-12 ? gm : 1e-12);
-}
-__device__ __forceinline__ float over_norm(float num, float gx, float gy) {
-  return num * __builtin_amdgcn_rsqf(fmaxf(fmaf(gx, gx, gy * gy), 1e-24f));
+// num / max(|g|, 1e-12), the square root and the quotient rounded exactly (a
+// hardware reciprocal square root in FP32 was ~1 % faster, but moved the
+// FP32 field of the 64^2 translation by 5x more in L-inf)
+template <typename T>
+__device__ __forceinline__ T over_norm(T num, T gx, T gy) {
+  const T gm = sqrt(fma(gx, gx, gy * gy));
+  return num / (gm > T(1e-12) ? gm : T(1e-12));
 }
 
 template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>

@@ -140,3 +140,29 @@ def test_batch_rejects_mismatched_plan(lib):
         b.set(0, s32, 5)
     with pytest.raises(lib.DugksError):
         b.tile_rows = 12
+
+
+def test_empty_batch_and_cleared_slots(lib):
+    """A batch with no grid attached steps as a no-op (graph replays and
+    single steps alike); a cleared slot stops advancing and keeps its state."""
+    import torch
+    from paper_2007_07760_amd.batch import Batch
+    b = Batch(3, lib.F32, lib.UPWIND3, lib.FLAG_MASS_FIX)
+    b.commit()
+    b.step(5, graph_steps=2)
+    st = b.sync()
+    assert int(np.abs(st).sum()) == 0
+    s = _solver(lib, GRIDS[1], 1, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3)
+    b.set(2, s, 100)
+    b.commit()
+    b.step(4)
+    st = b.sync()
+    assert int(st[2, 0]) == 4
+    b.clear(2)
+    b.commit()
+    frozen = s.distributions().clone()
+    b.step(3, graph_steps=3)
+    b.sync()
+    assert torch.equal(s.distributions(), frozen)
+    ref = _alone(lib, GRIDS[1], 1, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3, 4)
+    assert torch.equal(frozen, ref.distributions())

@@ -171,6 +171,30 @@ def test_edge_sizes(gpu, orc, shape, tile):
         _check(g, o, f"edge recon {recon}")
 
 
+@pytest.mark.parametrize("shape", [(65536, 8), (8, 65536)])
+def test_maximum_sides(gpu, orc, shape):
+    """The longest side the ABI takes (65536) against the shortest (8): 1130
+    strips of one row group, or one strip 65536 rows tall (strip columns and
+    their stores span the most rows), rotation and uniform flow."""
+    nx, ny = shape
+    phi0 = I.random_circles(nx, ny, 40, 2.0, 3.5, 3.0, seed=nx % 97 + ny % 89)
+    for recon, kind, prm in ((1, 0, (0.03, -0.02)), (2, 1, (1e-6, nx / 2, ny / 2))):
+        g, o = _pair(gpu, orc, nx, ny, 0.02, 3.0, 0.7, recon, kind, prm, phi0, twin=False)
+        g.step(3)
+        o.run(3)
+        _check(g, o, f"max side {nx}x{ny} recon {recon}")
+
+
+def test_zero_steps_is_a_no_op(gpu):
+    w = I.workload("c1")
+    g = gpu(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"], recon=w["recon"],
+            vel_kind=w["vel_kind"], vel_param=w["vel_param"]).init(w["phi0"]).step(5)
+    before = g.distributions().clone()
+    g.step(0)
+    assert g.step_index == 5
+    assert bool((g.distributions() == before).all())
+
+
 def test_cfl_one_and_theta_off(gpu, orc):
     nx, ny = 64, 40
     phi0 = I.random_smooth(nx, ny, seed=5)
