@@ -4,8 +4,10 @@ Workload (the headline configuration): one D2Q9 DUGKS T2 step of the
 conservative Allen-Cahn equation on a 4096 x 4096 periodic grid, upwind-3
 (third-order isotropic) reconstruction, W = 4, M = 0.01, C = 0.5, 64 random
 tanh circles (R 20-200 cells, seed 0) in rigid rotation (corner speed 0.05).
-State is resident in HBM before the timed region; the timed region is exactly
---steps calls of the step (one fused kernel each).  FP64 is the headline line;
+State is resident in HBM before the timed region, and the tile height of each
+plain-path run is measured on that state first (dugks_tune; the state is left
+unchanged); the timed region is exactly --steps calls of the step (one fused
+kernel each).  FP64 is the headline line;
 the FP32 form (FP32 storage, FP64 mass sums and the fused mass correction on
 every step) is reported in the same line, and so are the batched form (256
 uneven grids, 32-512 per side, one persistent kernel, hipGraph replays of 50
@@ -43,7 +45,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="tile height of the plain path (0: autotuned with dugks_tune)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
@@ -148,7 +151,7 @@ def profile_traffic_t3s3():
     return rec["stage_a"]["bytes_per_launch"] + rec["stage_b"]["bytes_per_launch"]
 
 
-def bench_t3s3(w, steps, warmup):
+def bench_t3s3(w, steps, warmup, tile_rows):
     """The DUGKS-T3S3 step (stage A + stage B kernels) on the headline field
     with M = T3S3_MOBILITY, FP64."""
     import torch
@@ -156,7 +159,8 @@ def bench_t3s3(w, steps, warmup):
     from paper_2007_07760_amd.solver import Solver
     s = Solver(w["nx"], w["ny"], T3S3_MOBILITY, w["width"], w["cfl"], recon=w["recon"],
                precision=C.F64, vel_kind=w["vel_kind"], vel_param=w["vel_param"],
-               scheme=C.T3S3).init(w["phi0"])
+               scheme=C.T3S3, tile_rows=tile_rows).init(w["phi0"])
+    rows = tile_rows or s.tune()
     wall, ev_ms = time_steps(s, steps, warmup)
     k_ms = time_kernel_only(s, min(steps, 50))
     lus = w["nx"] * w["ny"]
@@ -167,7 +171,7 @@ def bench_t3s3(w, steps, warmup):
             "ms_per_step": round(ev_ms / steps, 4), "dtype": "f64",
             "mobility": T3S3_MOBILITY, "kernels": "step_kernel stage A + stage B",
             "step_kernels_ms": round(k_ms, 4), "achieved": round(achieved, 1),
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "tile_rows": rows,
             "traffic": profile_traffic_t3s3(), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
 
 
@@ -314,6 +318,9 @@ def main():
                    recon=w["recon"], precision=prec, vel_kind=w["vel_kind"],
                    vel_param=w["vel_param"], tile_rows=args.tile_rows,
                    flags=C.FLAG_MASS_FIX if prec == C.F32 else 0).init(w["phi0"])
+        # tile height: measured on this state before the warm-up (dugks_tune
+        # leaves the state unchanged)
+        rows = args.tile_rows or s.tune()
         wall, ev_ms = time_steps(s, args.steps, args.warmup)
         k_ms = time_kernel_only(s, min(args.steps, 50))
         esize = 8 if prec == C.F64 else 4
@@ -321,7 +328,7 @@ def main():
         achieved = alg_bytes / (k_ms * 1e-3) / 1e9
         results[prec_name] = dict(
             wall=wall, ev_ms=ev_ms, kernel_ms=k_ms, achieved=achieved,
-            mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6,
+            mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6, tile_rows=rows,
             traffic=profile_traffic(prec_name))
         del s
         torch.cuda.empty_cache()
@@ -345,7 +352,7 @@ def main():
                                "upwind-3 isotropic reconstruction, W=4, M=0.01, C=0.5, "
                                "64 tanh circles in rigid rotation",
                    "nx": w["nx"], "ny": w["ny"], "recon": "upwind3",
-                   "tile_rows": args.tile_rows or "default"},
+                   "tile_rows": r["tile_rows"]},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["achieved"] / HBM_PEAK_GBS, 4),
@@ -363,9 +370,10 @@ def main():
                         "kernel_ms": round(f["kernel_ms"], 4),
                         "achieved": round(f["achieved"], 1),
                         "frac": round(f["achieved"] / HBM_PEAK_GBS, 4),
-                        "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4}
+                        "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4,
+                        "tile_rows": f["tile_rows"]}
     if not args.no_t3s3 and not args.only:
-        line["t3s3"] = bench_t3s3(w, args.steps, args.warmup)
+        line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows)
     if not args.no_batch and not args.only:
         line["batched"] = bench_batched(args.batch_steps)
     if not args.no_serve and not args.only:

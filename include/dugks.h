@@ -155,6 +155,21 @@ int dugks_init(const dugks_plan *plan, void *state, const double *phi0_dev,
 int dugks_step(const dugks_plan *plan, void *state, int64_t step,
                int64_t nsteps, void *stream);
 
+/* Autotuner of the tile height (rows one wavefront marches; results do not
+ * depend on it).  For the library default and every height 16..256 (steps of
+ * 8, at most ny), times `reps` launches of the step's kernels on `state` at
+ * `step` (the state of the plan built from `params`, any tile_rows) -- after
+ * 20 warm-up launches, twice per height, the better kept -- and writes the
+ * fastest height to rows_out; the caller builds its plan with it.
+ * The timed launches read the state at `step` and write only what the step
+ * itself overwrites before it reads it (the next-step buffer, T3S3's stage
+ * buffers, the mass partials); the fused correction's reduction does not run,
+ * so the state at `step` and its header are unchanged.  Blocks until done.
+ * Errors: EINVAL (NULL, misaligned state, step < 0, reps outside 1..1000,
+ * params invalid), EUNSUPPORTED, EDEVICE. */
+int dugks_tune(const dugks_params *params, void *state, int64_t step, int32_t reps,
+               int32_t *rows_out, void *stream);
+
 /* phi = sum_i of the stored distributions (Eq. 30; Eq. 30a for T3S3) of the
  * state at `step`, written to phi_out_dev as [ny][nx] dense elements of the
  * plan's precision.  Asynchronous. */

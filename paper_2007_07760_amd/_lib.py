@@ -81,13 +81,14 @@ def load() -> ctypes.CDLL:
     L.dugks_batch_tile_rows.argtypes = [vp]
     L.dugks_batch_set_tile_rows.argtypes = [vp, i32]
     L.dugks_batch_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
+    L.dugks_tune.argtypes = [P, vp, i64, i32, ctypes.POINTER(i32), vp]
     for name in ("dugks_plan_create", "dugks_init", "dugks_step", "dugks_phi",
                  "dugks_distributions",
                  "dugks_mass", "dugks_mass_correct", "dugks_mass0",
                  "dugks_batch_create", "dugks_batch_set", "dugks_batch_clear",
                  "dugks_batch_commit", "dugks_batch_step", "dugks_batch_steps",
                  "dugks_batch_tile_rows", "dugks_batch_set_tile_rows",
-                 "dugks_batch_tune"):
+                 "dugks_batch_tune", "dugks_tune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -219,6 +220,13 @@ def dugks_batch_set_tile_rows(batch: int, rows: int) -> None:
 def dugks_batch_tune(batch: int, reps: int, stream: int) -> int:
     rows = ctypes.c_int32()
     _check(load().dugks_batch_tune(batch, reps, ctypes.byref(rows), stream), "dugks_batch_tune")
+    return rows.value
+
+
+def dugks_tune(params, state: int, step: int, reps: int, stream: int) -> int:
+    rows = ctypes.c_int32()
+    _check(load().dugks_tune(ctypes.byref(params), state, step, reps, ctypes.byref(rows), stream),
+           "dugks_tune")
     return rows.value
 
 

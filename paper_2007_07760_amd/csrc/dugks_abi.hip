@@ -224,8 +224,10 @@ int default_tile_rows(const dugks_params& p, int nstrips) {
 }
 
 // ------------------------------------------------------------ launches
+// fix = false leaves out the fused mass correction's reduction (tile timing:
+// the header then keeps the correction the next real step applies)
 template <typename T, bool MFIX, int STAGE>
-int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s, bool fix = true) {
   const Layout& L = P->L;
   StepArgs<T> a = step_args<T>(P, STAGE);
   StepBufs<T> q = step_bufs<T>(P, state, n);
@@ -252,7 +254,7 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
     default: DUGKS_LAUNCH(DUGKS_CENTRAL4); break;
   }
 #undef DUGKS_LAUNCH
-  if (MFIX)
+  if (MFIX && fix)
     hipLaunchKernelGGL(mass_fix_strips_kernel, dim3(L.tl.nstrips), dim3(LANES), 0, s,
                        part, L.ngroups, L.tl.nstrips, at<double>(state, L.off_strips), hd,
                        (double)P->p.nx * (double)P->p.ny);
@@ -260,13 +262,14 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
 }
 
 template <typename T>
-int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s) {
+int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s, bool fix = true) {
   if (P->p.scheme == DUGKS_T3S3) {
     int rc = launch_stage<T, false, STAGE_A>(P, state, n, s);
     return rc ? rc : launch_stage<T, false, STAGE_B>(P, state, n, s);
   }
-  return (P->p.flags & DUGKS_FLAG_MASS_FIX) ? launch_stage<T, true, STAGE_T2>(P, state, n, s)
-                                           : launch_stage<T, false, STAGE_T2>(P, state, n, s);
+  return (P->p.flags & DUGKS_FLAG_MASS_FIX)
+             ? launch_stage<T, true, STAGE_T2>(P, state, n, s, fix)
+             : launch_stage<T, false, STAGE_T2>(P, state, n, s);
 }
 
 template <typename T>
@@ -487,6 +490,66 @@ int dugks_step(const dugks_plan* plan, void* state, int64_t step, int64_t nsteps
     if (rc) return rc;
   }
   return DUGKS_OK;
+}
+
+int dugks_tune(const dugks_params* params, void* state, int64_t step, int32_t reps,
+               int32_t* rows_out, void* stream) {
+  if (!params || !state || !rows_out || !aligned(state) || step < 0 || reps < 1 || reps > 1000)
+    return DUGKS_EINVAL;
+  const int rc0 = validate(params);
+  if (rc0) return rc0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // candidates: the default height, then 16..256 rows in steps of MASS_GROUP
+  // (as the plans round them: duplicates dropped)
+  std::vector<dugks_plan*> plans;
+  int rc = DUGKS_OK;
+  for (int c = 0; c <= std::min(256, params->ny) && !rc; c = (c == 0 ? 16 : c + MASS_GROUP)) {
+    dugks_params q = *params;
+    q.tile_rows = c;
+    dugks_plan* P = nullptr;
+    if ((rc = dugks_plan_create(&q, &P))) break;
+    bool dup = false;
+    for (dugks_plan* o : plans) dup = dup || o->seg_rows == P->seg_rows;
+    if (dup)
+      dugks_plan_destroy(P);
+    else
+      plans.push_back(P);
+  }
+  auto launch = [&](const dugks_plan* P) {
+    return P->p.precision == DUGKS_F64 ? launch_step<double>(P, state, step, s, false)
+                                       : launch_step<float>(P, state, step, s, false);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = DUGKS_EDEVICE;
+  // the clocks ramp up over the first launches after idle: warm up first, then
+  // time every candidate twice (forward, then backward) and keep its best
+  for (int k = 0; k < 20 && !rc; k++) rc = launch(plans[0]);
+  std::vector<float> best(plans.size(), 0.0f);
+  for (int pass = 0; pass < 2 && !rc; pass++) {
+    for (size_t j = 0; j < plans.size() && !rc; j++) {
+      const size_t i = pass == 0 ? j : plans.size() - 1 - j;
+      rc = launch(plans[i]);   // one untimed launch at this shape
+      if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = DUGKS_EDEVICE;
+      for (int k = 0; k < reps && !rc; k++) rc = launch(plans[i]);
+      if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = DUGKS_EDEVICE;
+      float ms = 0.0f;
+      if (!rc && (hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = DUGKS_EDEVICE;
+      if (!rc && (pass == 0 || ms < best[i])) best[i] = ms;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!rc) {
+    size_t b = 0;
+    for (size_t i = 1; i < plans.size(); i++)
+      if (best[i] < best[b]) b = i;
+    *rows_out = plans[b]->seg_rows;
+  }
+  for (dugks_plan* P : plans) dugks_plan_destroy(P);
+  return rc;
 }
 
 int dugks_phi(const dugks_plan* plan, const void* state, int64_t step, void* phi_out_dev,

@@ -97,6 +97,16 @@ def test_calls_reject_null_before_the_device(lib):
         assert lib.dugks_batch_step(None, 1, 0, None) == C.EINVAL
         assert lib.dugks_batch_commit(None, None) == C.EINVAL
         assert lib.dugks_batch_tile_rows(None) == -1
+        rows = __import__("ctypes").c_int32()
+        prm = _p()
+        by = __import__("ctypes").byref
+        assert lib.dugks_tune(None, 4096, 0, 1, by(rows), None) == C.EINVAL
+        assert lib.dugks_tune(by(prm), None, 0, 1, by(rows), None) == C.EINVAL
+        assert lib.dugks_tune(by(prm), 4096 + 8, 0, 1, by(rows), None) == C.EINVAL
+        assert lib.dugks_tune(by(prm), 4096, -1, 1, by(rows), None) == C.EINVAL
+        assert lib.dugks_tune(by(prm), 4096, 0, 0, by(rows), None) == C.EINVAL
+        assert lib.dugks_tune(by(prm), 4096, 0, 1, None, None) == C.EINVAL
+        assert lib.dugks_tune(by(_p(cfl=2.0)), 4096, 0, 1, by(rows), None) == C.EINVAL
         out = __import__("ctypes").c_void_p()
         assert lib.dugks_batch_create(0, 0, 0, 0, __import__("ctypes").byref(out)) == C.EINVAL
         assert lib.dugks_batch_create(4, 0, 0, 8, __import__("ctypes").byref(out)) == C.EINVAL
