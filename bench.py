@@ -46,7 +46,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--tile-rows", type=int, default=0,
-                    help="tile height of the plain path (0: autotuned with dugks_tune)")
+                    help="tile height of the plain FP64 run (0: autotuned with dugks_tune)")
+    ap.add_argument("--tile-rows-f32", type=int, default=0,
+                    help="tile height of the plain FP32 run (0: autotuned)")
+    ap.add_argument("--tile-rows-t3s3", type=int, default=0,
+                    help="tile height of the T3S3 run (0: autotuned)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
@@ -121,9 +125,10 @@ def copy_bandwidth():
     return gbs
 
 
-def _profile_record(name: str):
+def _profile_record(name: str, tile_rows: int):
     """A committed rocprofv3 PMC summary (profiles/<name>.json) if it was taken
-    with the kernel sources of this build, else None."""
+    with the kernel sources of this build and the same tile height (the halo
+    rows re-read depend on it), else None."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name + ".json")
     if not os.path.exists(path):
         return None
@@ -132,20 +137,22 @@ def _profile_record(name: str):
         from paper_2007_07760_amd import kernel_fingerprint
         if rec.get("kernel_fingerprint") != kernel_fingerprint():
             return None
+        if rec.get("tile_rows") != tile_rows:
+            return None
         return rec
     except Exception:
         return None
 
 
-def profile_traffic(precision: str):
+def profile_traffic(precision: str, tile_rows: int):
     """HBM bytes per launch of the T2 step kernel (profiles/traffic_h1_<precision>.json)."""
-    rec = _profile_record(f"traffic_h1_{precision}")
+    rec = _profile_record(f"traffic_h1_{precision}", tile_rows)
     return rec.get("bytes_per_launch") if rec else None
 
 
-def profile_traffic_t3s3():
+def profile_traffic_t3s3(tile_rows: int):
     """HBM bytes of one T3S3 step (stage A + stage B launches)."""
-    rec = _profile_record("traffic_h1_t3s3_f64")
+    rec = _profile_record("traffic_h1_t3s3_f64", tile_rows)
     if not rec:
         return None
     return rec["stage_a"]["bytes_per_launch"] + rec["stage_b"]["bytes_per_launch"]
@@ -172,7 +179,7 @@ def bench_t3s3(w, steps, warmup, tile_rows):
             "mobility": T3S3_MOBILITY, "kernels": "step_kernel stage A + stage B",
             "step_kernels_ms": round(k_ms, 4), "achieved": round(achieved, 1),
             "frac": round(achieved / HBM_PEAK_GBS, 4), "tile_rows": rows,
-            "traffic": profile_traffic_t3s3(), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
+            "traffic": profile_traffic_t3s3(rows), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
 
 
 def bench_batched(steps):
@@ -314,13 +321,14 @@ def main():
     for prec_name, prec in (("f64", C.F64), ("f32", C.F32)):
         if args.only and args.only != prec_name:
             continue
+        tile = args.tile_rows if prec == C.F64 else args.tile_rows_f32
         s = Solver(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                    recon=w["recon"], precision=prec, vel_kind=w["vel_kind"],
-                   vel_param=w["vel_param"], tile_rows=args.tile_rows,
+                   vel_param=w["vel_param"], tile_rows=tile,
                    flags=C.FLAG_MASS_FIX if prec == C.F32 else 0).init(w["phi0"])
         # tile height: measured on this state before the warm-up (dugks_tune
         # leaves the state unchanged)
-        rows = args.tile_rows or s.tune()
+        rows = tile or s.tune()
         wall, ev_ms = time_steps(s, args.steps, args.warmup)
         k_ms = time_kernel_only(s, min(args.steps, 50))
         esize = 8 if prec == C.F64 else 4
@@ -329,7 +337,7 @@ def main():
         results[prec_name] = dict(
             wall=wall, ev_ms=ev_ms, kernel_ms=k_ms, achieved=achieved,
             mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6, tile_rows=rows,
-            traffic=profile_traffic(prec_name))
+            traffic=profile_traffic(prec_name, rows))
         del s
         torch.cuda.empty_cache()
     copy_gbs = copy_bandwidth()
@@ -373,7 +381,7 @@ def main():
                         "traffic": f["traffic"], "bytes_per_lu": WORDS_PER_LU * 4,
                         "tile_rows": f["tile_rows"]}
     if not args.no_t3s3 and not args.only:
-        line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows)
+        line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows_t3s3)
     if not args.no_batch and not args.only:
         line["batched"] = bench_batched(args.batch_steps)
     if not args.no_serve and not args.only:
