@@ -61,19 +61,24 @@ class Solver:
         self.step_index += nsteps
         return self
 
+    def retile(self, rows: int) -> "Solver":
+        """Rebuild the plan with another tile height (the state layout does not
+        depend on it, and results do not either)."""
+        if rows != self.params.tile_rows:
+            self.params.tile_rows = int(rows)
+            plan = C.dugks_plan_create(self.params)
+            torch.cuda.current_stream().synchronize()   # init's staged copy has run
+            C.dugks_plan_destroy(self.plan)
+            self.plan = plan
+        return self
+
     def tune(self, reps: int = 5) -> int:
         """Time the step's kernels on this state for a range of tile heights
         (dugks_tune, which leaves the state unchanged) and rebuild the plan
         with the fastest; returns the height."""
         rows = C.dugks_tune(self.params, self.state.data_ptr(), self.step_index, reps,
                             self.stream())
-        if rows != self.params.tile_rows:
-            self.params.tile_rows = rows
-            plan = C.dugks_plan_create(self.params)
-            # dugks_tune waited for the stream, so dugks_init's staged copy of
-            # the old plan has executed
-            C.dugks_plan_destroy(self.plan)
-            self.plan = plan
+        self.retile(rows)
         return rows
 
     def phi(self) -> torch.Tensor:
