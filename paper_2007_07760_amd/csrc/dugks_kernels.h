@@ -192,15 +192,14 @@ struct Marcher {
 
   const StepArgs<T>& a;
   const T* __restrict__ src;
-  T* __restrict__ dst;
-  T* __restrict__ dst2;     // stage A: Q
-  const T* __restrict__ aux;  // stage B: Q
   cptr<T> cf;
   const T* __restrict__ tabx;
   cptr<T> taby;
   T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
   int ocol;                 // owned lanes: column within the strip
+  // the strip's own chunk column of the output (rdst), of stage A's second
+  // output Q (rdst2) and of stage B's input Q (raux); the strip's mass partials
   rsrc_t rdst, rdst2, rpart, raux;
   int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
   bool owned;
@@ -525,7 +524,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
                                            double* __restrict__ part, double pend,
                                            double fitmax, int strip,
                                            int seg, T (*s_bfp)[9][LROW]) {
-  Marcher<T, R, MFIX, STAGE> m{a, src, dst, dst2, aux, as_const(cf), tabx, as_const(taby),
+  Marcher<T, R, MFIX, STAGE> m{a, src, as_const(cf), tabx, as_const(taby),
                                s_bfp};
   const int lane = threadIdx.x;
   const int x0 = strip * OWN;
