@@ -233,10 +233,12 @@ def test_c2_rotation_first_steps(gpu, orc):
     w = I.workload("c2")
     g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                  w["recon"], w["vel_kind"], w["vel_param"], w["phi0"])
-    for steps in (1, 99, 100):
-        g.step(steps)
-        o.run(steps)
-        _check(g, o, f"c2 +{steps}")
+    done = 0
+    for target in (1, 100, 200, 500):     # the first 500 steps of the turn
+        g.step(target - done)
+        o.run(target - done)
+        done = target
+        _check(g, o, f"c2 step {target}")
 
 
 def test_c3_single_vortex_central4(gpu, orc):
@@ -244,9 +246,10 @@ def test_c3_single_vortex_central4(gpu, orc):
     for recon in (2, 1):
         g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                      recon, w["vel_kind"], w["vel_param"], w["phi0"])
-        g.step(40)
-        o.run(40)
-        _check(g, o, f"c3 recon {recon}")
+        for target in (40, 200):          # the first 200 steps
+            g.step(target - (40 if target == 200 else 0))
+            o.run(target - (40 if target == 200 else 0))
+            _check(g, o, f"c3 recon {recon} step {target}")
 
 
 def test_mass_conservation_fp64(gpu):
