@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--only-batch", action="store_true",
                     help="the batched section alone (profiling runs)")
     ap.add_argument("--no-t3s3", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
                     help="time one precision only (profiling runs)")
@@ -208,6 +209,28 @@ def bench_t3s3(w, steps, warmup, tile_rows):
             "step_kernels_ms": round(k_ms, 4), "achieved": round(achieved, 1),
             "frac": round(achieved / HBM_PEAK_GBS, 4), "tile_rows": rows, "tile_source": source,
             "traffic": profile_traffic_t3s3(rows), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
+
+
+def bench_shard_share(w, steps, warmup):
+    """FP64 on one GPU's share of an 8-way row-slab split of the headline grid:
+    4096 x 512 rows of the same field, periodic (a slab would take its 3 halo
+    rows from its neighbours instead; the kernel's work per row is the same)."""
+    import torch
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd.solver import Solver
+    ny = w["ny"] // 8
+    s = Solver(w["nx"], ny, w["mobility"], w["width"], w["cfl"], recon=w["recon"],
+               precision=C.F64, vel_kind=w["vel_kind"], vel_param=w["vel_param"]).init(
+                   w["phi0"][:ny].copy())
+    rows = s.tune()
+    wall, ev_ms = time_steps(s, steps, warmup)
+    del s
+    torch.cuda.empty_cache()
+    lus = w["nx"] * ny
+    return {"workload": f"{w['nx']}x{ny}: one GPU's share of an 8-way row-slab split of the "
+                        f"{w['nx']}x{w['ny']} grid (halo exchange not included)",
+            "value": round(lus * steps / (ev_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ev_ms / steps, 4), "dtype": "f64", "tile_rows": rows}
 
 
 def bench_batched(steps):
@@ -410,6 +433,8 @@ def main():
                         "tile_rows": f["tile_rows"], "tile_source": f["tile_source"]}
     if not args.no_t3s3 and not args.only:
         line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows_t3s3)
+    if not args.no_shard and not args.only:
+        line["shard_share"] = bench_shard_share(w, args.steps, args.warmup)
     if not args.no_batch and not args.only:
         line["batched"] = bench_batched(args.batch_steps)
     if not args.no_serve and not args.only:
