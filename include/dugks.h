@@ -208,10 +208,11 @@ int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
  * need them: a batch has `capacity` slots, each holding a (plan, state) pair
  * of the batch's precision and reconstruction, the step the state is at and
  * the step to stop at.  One persistent kernel takes the tiles of every active
- * grid from a work list in device memory (taller tiles first); a second, tiny
- * kernel then advances each active slot's step counter (and applies the fused
- * mass correction of DUGKS_FLAG_MASS_FIX batches).  Results are bitwise those
- * of dugks_step on the same plan and state.
+ * grid from a work list in device memory (taller tiles first) -- for
+ * DUGKS_BATCH_T3S3 batches one such kernel per stage; a last, tiny kernel then
+ * advances each active slot's step counter (and applies the fused mass
+ * correction of DUGKS_FLAG_MASS_FIX batches).  Results are bitwise those of
+ * dugks_step on the same plan and state.
  *  - The batch allocates a small amount of device memory of its own (slot
  *    descriptors, step counters, work list) on the device current at
  *    dugks_batch_create; every later call expects that device to be current.
@@ -223,9 +224,15 @@ int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
  *  - A batch is not thread-safe; calls on one batch must be serialised. */
 typedef struct dugks_batch dugks_batch;
 
-/* Create a batch of `capacity` slots (1..65536), all empty.  flags: 0 or
- * DUGKS_FLAG_MASS_FIX (then every attached plan must carry it, else none may).
- * Errors: EINVAL, ENOMEM, EDEVICE. */
+/* Batch flag: the batch advances DUGKS-T3S3 plans (two stage kernels per
+ * batch step); without it, T2 plans. */
+#define DUGKS_BATCH_T3S3 4u
+
+/* Create a batch of `capacity` slots (1..65536), all empty.  flags: 0,
+ * DUGKS_FLAG_MASS_FIX (then every attached plan must carry it, else none may)
+ * or DUGKS_BATCH_T3S3 (then every attached plan is a T3S3 plan).  Errors:
+ * EINVAL, EUNSUPPORTED (DUGKS_FLAG_MASS_FIX with DUGKS_BATCH_T3S3), ENOMEM,
+ * EDEVICE. */
 int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon,
                        uint32_t flags, dugks_batch **out);
 /* Wait for the device, then free the batch and its device memory. */
@@ -234,8 +241,8 @@ void dugks_batch_destroy(dugks_batch *batch);
 /* Attach `state` (initialised by dugks_init for `plan`, currently at `step`)
  * to `slot`; the grid advances until its counter reaches `target` (>= step).
  * Replaces whatever the slot held.  Errors: EINVAL (range, NULL, misaligned
- * state, plan of another precision / reconstruction / mass-fix flag),
- * EUNSUPPORTED (T3S3 plans: batches run T2 only). */
+ * state, plan of another precision / reconstruction / mass-fix flag / time
+ * scheme than the batch's). */
 int dugks_batch_set(dugks_batch *batch, int32_t slot, const dugks_plan *plan,
                     void *state, int64_t step, int64_t target);
 /* Empty `slot`.  Errors: EINVAL. */

@@ -22,6 +22,7 @@ VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = rang
 T2, T3S3 = 0, 1
 FLAG_DTPHIU_ZERO = 1
 FLAG_MASS_FIX = 2
+BATCH_T3S3 = 4      # batch flag: the batch advances T3S3 plans
 
 
 class DugksError(RuntimeError):

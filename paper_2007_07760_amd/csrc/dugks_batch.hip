@@ -33,6 +33,7 @@ struct Slot {
 
 struct dugks_batch {
   int cap = 0, precision = 0, recon = 0;
+  int scheme = DUGKS_T2;              // every attached plan's time scheme
   bool mfix = false;
   int device = 0;
   size_t desc_bytes = 0;              // sizeof(GridDesc<T>)
@@ -70,11 +71,20 @@ GridDesc<T> make_desc(const Slot& s, int rows) {
   if (!s.plan) return d;
   const dugks_plan* P = s.plan;
   const Layout& L = P->L;
-  d.a = step_args<T>(P);
+  const bool t3 = P->p.scheme == DUGKS_T3S3;
+  d.a = step_args<T>(P, t3 ? STAGE_A : STAGE_T2);
+  d.b = step_args<T>(P, t3 ? STAGE_B : STAGE_T2);
   const int seg = std::min(rows, P->p.ny);
-  d.a.seg_rows = seg;
-  d.a.nsegs = (P->p.ny + seg - 1) / seg;
-  d.a.nlogical = d.a.nstrips * d.a.nsegs;
+  for (StepArgs<T>* a : {&d.a, &d.b}) {
+    a->seg_rows = seg;
+    a->nsegs = (P->p.ny + seg - 1) / seg;
+    a->nlogical = a->nstrips * a->nsegs;
+  }
+  if (t3) {
+    d.mid = at<T>(s.state, L.off_mid);
+    d.q = at<T>(s.state, L.off_q);
+    d.cf2 = at<T>(s.state, L.off_coef2);
+  }
   d.buf[0] = at<T>(s.state, L.off_buf[0]);
   d.buf[1] = at<T>(s.state, L.off_buf[1]);
   d.cf = at<T>(s.state, L.off_coef);
@@ -186,8 +196,16 @@ int upload(dugks_batch* B, hipStream_t s) {
 
 template <typename T, int R, bool MFIX>
 int launch_batch_step(dugks_batch* B, hipStream_t s, bool finish) {
-  hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
-                     static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_ctl, B->d_head);
+  const GridDesc<T>* desc = static_cast<const GridDesc<T>*>(B->d_desc);
+  if (B->scheme == DUGKS_T3S3) {   // the two stages over every tile, in turn
+    hipLaunchKernelGGL((batch_step_kernel<T, R, false, STAGE_A>), dim3(B->grid_blocks),
+                       dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
+    hipLaunchKernelGGL((batch_step_kernel<T, R, false, STAGE_B>), dim3(B->grid_blocks),
+                       dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
+  } else {
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
+                       desc, B->d_steps, B->d_ctl, B->d_head);
+  }
   if (finish)
     hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(B->cap), dim3(FIX_THREADS), 0, s,
                        static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_head);
@@ -217,14 +235,26 @@ int batch_launch(dugks_batch* B, hipStream_t s, bool finish) {
 }
 
 template <typename T, int R, bool MFIX>
-int occupancy(int* per_cu) {
+int occupancy(int* per_cu, int scheme) {
+  if (scheme == DUGKS_T3S3) {   // the smaller of the two stages' residencies
+    int a = 0, b = 0;
+    int rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &a, reinterpret_cast<const void*>(&batch_step_kernel<T, R, false, STAGE_A>), LANES, 0));
+    if (!rc)
+      rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b, reinterpret_cast<const void*>(&batch_step_kernel<T, R, false, STAGE_B>), LANES,
+          0));
+    *per_cu = std::min(a, b);
+    return rc;
+  }
   return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       per_cu, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX>), LANES, 0));
 }
 
 int batch_occupancy(const dugks_batch* B, int* per_cu) {
-#define DUGKS_OCC(TT, RR) \
-  return B->mfix ? occupancy<TT, RR, true>(per_cu) : occupancy<TT, RR, false>(per_cu)
+#define DUGKS_OCC(TT, RR)                                   \
+  return B->mfix ? occupancy<TT, RR, true>(per_cu, B->scheme) \
+                 : occupancy<TT, RR, false>(per_cu, B->scheme)
 #define DUGKS_OCC_R(TT)                                 \
   switch (B->recon) {                                   \
     case DUGKS_CENTRAL2: DUGKS_OCC(TT, DUGKS_CENTRAL2);  \
@@ -298,14 +328,16 @@ int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint3
   if (!out) return DUGKS_EINVAL;
   *out = nullptr;
   if (capacity < 1 || capacity > 65536 || precision < 0 || precision > 1 || recon < 0 ||
-      recon > 2 || (flags & ~DUGKS_FLAG_MASS_FIX))
+      recon > 2 || (flags & ~(DUGKS_FLAG_MASS_FIX | DUGKS_BATCH_T3S3)))
     return DUGKS_EINVAL;
+  if ((flags & DUGKS_FLAG_MASS_FIX) && (flags & DUGKS_BATCH_T3S3)) return DUGKS_EUNSUPPORTED;
   dugks_batch* B = new (std::nothrow) dugks_batch();
   if (!B) return DUGKS_ENOMEM;
   B->cap = capacity;
   B->precision = precision;
   B->recon = recon;
   B->mfix = (flags & DUGKS_FLAG_MASS_FIX) != 0;
+  B->scheme = (flags & DUGKS_BATCH_T3S3) ? DUGKS_T3S3 : DUGKS_T2;
   B->slots.resize(capacity);
   B->desc_bytes = precision == DUGKS_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
   int rc = DUGKS_OK;
@@ -357,9 +389,9 @@ int dugks_batch_set(dugks_batch* batch, int32_t slot, const dugks_plan* plan, vo
       step < 0 || target < step)
     return DUGKS_EINVAL;
   if (plan->p.precision != batch->precision || plan->p.recon != batch->recon ||
-      ((plan->p.flags & DUGKS_FLAG_MASS_FIX) != 0) != batch->mfix)
+      ((plan->p.flags & DUGKS_FLAG_MASS_FIX) != 0) != batch->mfix ||
+      plan->p.scheme != batch->scheme)
     return DUGKS_EINVAL;
-  if (plan->p.scheme != DUGKS_T2) return DUGKS_EUNSUPPORTED;
   Slot& s = batch->slots[slot];
   s.plan = plan;
   s.state = state;
@@ -434,15 +466,15 @@ int dugks_batch_tune(dugks_batch* batch, int32_t reps, int32_t* rows_out, void* 
     if ((rc = commit(batch, s))) break;
     // one untimed pass, then the timed passes
     if ((rc = batch_launch(batch, s, false))) break;
-    // the step kernel alone leaves the queue head at its end: rewind it
-    if (hipMemsetAsync(batch->d_head, 0, sizeof(unsigned), s) != hipSuccess) {
+    // the step kernels alone leave the queue heads at their ends: rewind them
+    if (hipMemsetAsync(batch->d_head, 0, 2 * sizeof(unsigned), s) != hipSuccess) {
       rc = DUGKS_EDEVICE;
       break;
     }
     (void)hipEventRecord(e0, s);
     for (int r = 0; r < reps && rc == DUGKS_OK; r++) {
       rc = batch_launch(batch, s, false);
-      if (!rc && hipMemsetAsync(batch->d_head, 0, sizeof(unsigned), s) != hipSuccess)
+      if (!rc && hipMemsetAsync(batch->d_head, 0, 2 * sizeof(unsigned), s) != hipSuccess)
         rc = DUGKS_EDEVICE;
     }
     (void)hipEventRecord(e1, s);

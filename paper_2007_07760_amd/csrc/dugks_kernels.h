@@ -727,8 +727,12 @@ __device__ __forceinline__ void mass_fix_block(const double* __restrict__ part,
 // memory until the list is exhausted.
 template <typename T>
 struct GridDesc {
-  StepArgs<T> a;
+  StepArgs<T> a;      // T2, or T3S3 stage A
+  StepArgs<T> b;      // T3S3 stage B
   T* buf[2];
+  T* mid;             // T3S3: f~ at t + dt/3 (stage A -> B)
+  T* q;               // T3S3: Q (stage A -> B)
+  const T* cf2;       // T3S3: stage B's stencil table
   const T* cf;
   const T* tabx;
   const T* taby;
@@ -755,11 +759,13 @@ struct BatchCtl {
   int32_t pad;
 };
 
-template <typename T, int R, bool MFIX>
+// One batch step (STAGE_T2), or one stage of a T3S3 batch step, over the work
+// list; the two T3S3 stages take their items from separate queue heads.
+template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
 __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_step_kernel(
     const GridDesc<T>* __restrict__ desc, const SlotStep* __restrict__ steps,
     const BatchCtl* __restrict__ ctl, unsigned* __restrict__ head) {
-  constexpr int RB = Marcher<T, R, MFIX>::RB;
+  constexpr int RB = Marcher<T, R, MFIX, STAGE>::RB;
   __shared__ T s_bfp[RB][9][LROW];
   for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
   __syncthreads();
@@ -769,23 +775,31 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
   const cptr<BatchItem> items = as_const(c->items);
   const unsigned nitems = (unsigned)c->nitems;
   const cptr<SlotStep> st = as_const(steps);
+  unsigned* qhead = head + (STAGE == STAGE_B ? 1 : 0);
   for (;;) {
     unsigned it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(head, 1u);
+    if (threadIdx.x == 0) it = atomicAdd(qhead, 1u);
     it = __builtin_amdgcn_readfirstlane(it);
     if (it >= nitems) break;
     const BatchItem w = load_const(items + it);
     const int64_t n = st[w.slot].n;
     if (n >= st[w.slot].target) continue;
     const cptr<GridDesc<T>> d = as_const(desc) + w.slot;
-    const StepArgs<T> a = load_const(as_const(&d->a));
+    const StepArgs<T> a = load_const(as_const(STAGE == STAGE_B ? &d->b : &d->a));
     const int strip = w.tile % a.nstrips;
     const int seg = w.tile / a.nstrips;
     const int b = (int)(n & 1);
     const double pend = MFIX ? d->hdr->pending : 0.0;
     const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
-    march_tile<T, R, MFIX>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf, d->tabx,
-                           d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+    if (STAGE == STAGE_T2)
+      march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf,
+                                    d->tabx, d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+    else if (STAGE == STAGE_A)   // f^^n -> f~(t'), Q
+      march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->mid, d->q, nullptr, d->cf, d->tabx,
+                                    d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+    else                         // f~(t'), Q -> f^^{n+1}
+      march_tile<T, R, MFIX, STAGE>(a, n, d->mid, d->buf[b ^ 1], nullptr, d->q, d->cf2,
+                                    d->tabx, d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
     // the next item's ring starts from its own rows; order this tile's LDS
     // reads before them
     wave_sync();
@@ -799,7 +813,7 @@ __global__ __launch_bounds__(FIX_THREADS) void batch_finish_kernel(
     const GridDesc<T>* __restrict__ desc, SlotStep* __restrict__ steps,
     unsigned* __restrict__ head) {
   const int slot = blockIdx.x;
-  if (slot == 0 && threadIdx.x == 0) *head = 0u;
+  if (slot == 0 && threadIdx.x < 2) head[threadIdx.x] = 0u;   // both queue heads
   const int64_t n = steps[slot].n;
   if (n >= steps[slot].target) return;
   if (MFIX) {

@@ -2,11 +2,11 @@
 
 Each experiment is defined by the paper's dimensionless parameters (Pe = U0 L0 / M,
 Cn = W / L0, one period T_f = L0 / U0) and measured with the L2 error of Eq. 41
-between the final and the initial order parameter.  For the T2 schemes a whole
-table -- grids of different sizes, CFL numbers and periods -- runs as one FP64
-batch (one persistent kernel per step over every grid; each grid stops at its
-own period); T3S3 entries run one grid at a time, and those with dt >= 12 tau,
-which the scheme does not allow, are left out as in the paper.
+between the final and the initial order parameter.  A whole table of one
+scheme -- grids of different sizes, CFL numbers and periods -- runs as one FP64
+batch (one persistent kernel per step, or per stage for T3S3, over every grid;
+each grid stops at its own period).  T3S3 entries with dt >= 12 tau, which the
+scheme does not allow, are left out as in the paper.
 
   translation  Sec. III.A: circle R = L0/5 at the centre, u = (U0, U0), one
                period T_f (Tables I-III).
@@ -108,36 +108,39 @@ def run_alone(configs: list[dict], flags: int = 0) -> list[float | None]:
 
 
 def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float | None]:
-    """Run every configuration (one reconstruction) and return E_phi of each
-    after its own step count: T2 configurations in one FP64 batch, T3S3 ones
-    alone.  flags: plan flags (DUGKS_FLAG_DTPHIU_ZERO drops d(phi u)/dt from
-    the source)."""
+    """Run every configuration (one reconstruction, one time scheme) in one
+    FP64 batch and return E_phi of each after its own step count; None where
+    the scheme does not allow it.  flags: plan flags (DUGKS_FLAG_DTPHIU_ZERO
+    drops d(phi u)/dt from the source)."""
     if not configs:
         return []
-    if any(c.get("scheme", C.T2) != C.T2 for c in configs):
-        return run_alone(configs, flags)
     recon = configs[0]["recon"]
-    assert all(c["recon"] == recon for c in configs)
-    b = Batch(len(configs), C.F64, recon, 0)
-    sol, p0 = [], []
+    scheme = configs[0].get("scheme", C.T2)
+    assert all(c["recon"] == recon and c.get("scheme", C.T2) == scheme for c in configs)
+    b = Batch(len(configs), C.F64, recon, C.BATCH_T3S3 if scheme == C.T3S3 else 0)
+    sol, p0 = [None] * len(configs), [None] * len(configs)
     for k, c in enumerate(configs):
+        if not allowed(c):
+            continue
         phi0 = c["phi0"]()
         s = Solver(c["nx"], c["ny"], c["mobility"], c["width"], c["cfl"], recon=recon,
                    precision=C.F64, vel_kind=c["vel_kind"], vel_param=c["vel_param"],
-                   flags=flags).init(phi0)
+                   flags=flags, scheme=scheme).init(phi0)
         b.set(k, s, c["steps"])
-        sol.append(s)
-        p0.append(phi0)
+        sol[k], p0[k] = s, phi0
     b.commit()
-    left = max(c["steps"] for c in configs)
+    left = max(c["steps"] for c, s in zip(configs, sol) if s is not None) if any(sol) else 0
     while left > 0:
         chunk = min(left, 20 * graph_steps)
         b.step(chunk, graph_steps=graph_steps)
         left -= chunk
     st = b.sync()
-    assert all(int(st[k, 0]) == c["steps"] for k, c in enumerate(configs))
     out = []
-    for s, c, phi0 in zip(sol, configs, p0):
+    for k, (s, c, phi0) in enumerate(zip(sol, configs, p0)):
+        if s is None:
+            out.append(None)
+            continue
+        assert int(st[k, 0]) == c["steps"]
         out.append(_e_final(c, s.phi().cpu().numpy(), phi0))
     del b, sol
     torch.cuda.empty_cache()

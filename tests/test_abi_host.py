@@ -110,6 +110,8 @@ def test_calls_reject_null_before_the_device(lib):
         out = __import__("ctypes").c_void_p()
         assert lib.dugks_batch_create(0, 0, 0, 0, __import__("ctypes").byref(out)) == C.EINVAL
         assert lib.dugks_batch_create(4, 0, 0, 8, __import__("ctypes").byref(out)) == C.EINVAL
+        assert lib.dugks_batch_create(4, 0, 1, C.FLAG_MASS_FIX | C.BATCH_T3S3,
+                                      __import__("ctypes").byref(out)) == C.EUNSUPPORTED
     finally:
         C.dugks_plan_destroy(plan)
 

@@ -166,3 +166,49 @@ def test_empty_batch_and_cleared_slots(lib):
     assert torch.equal(s.distributions(), frozen)
     ref = _alone(lib, GRIDS[1], 1, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3, 4)
     assert torch.equal(frozen, ref.distributions())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_t3s3_batch_equals_alone(lib, precision):
+    """DUGKS-T3S3 grids in a DUGKS_BATCH_T3S3 batch (stage A and stage B
+    kernels over all grids per batch step, graph replays) equal their alone
+    runs bitwise, with targets that stop grids at different steps."""
+    import torch
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+
+    def make(k, g):
+        nx, ny, kind, prm = g
+        return Solver(nx, ny, 0.02, 4.0, 0.5, recon=lib.UPWIND3, precision=precision,
+                      vel_kind=kind, vel_param=prm, scheme=lib.T3S3).init(_phi0(nx, ny, k))
+
+    print(f"case T3S3 batch precision={precision}", flush=True)
+    b = Batch(len(GRIDS), precision, lib.UPWIND3, lib.BATCH_T3S3)
+    targets = [9 + 3 * k for k in range(len(GRIDS))]
+    sol = []
+    for k, g in enumerate(GRIDS):
+        s = make(k, g)
+        b.set(k, s, targets[k])
+        sol.append(s)
+    b.commit()
+    b.step(max(targets), graph_steps=4)
+    st = b.sync()
+    for k, g in enumerate(GRIDS):
+        assert int(st[k, 0]) == targets[k]
+        ref = make(k, g).step(targets[k])
+        assert torch.equal(sol[k].distributions(), ref.distributions()), (k, g)
+    rows = b.tune(reps=1)
+    assert rows > 0
+
+
+def test_batch_scheme_must_match(lib):
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+    b = Batch(2, lib.F64, lib.UPWIND3, lib.BATCH_T3S3)
+    t2 = Solver(40, 32, 0.02, 4.0, 0.5, recon=lib.UPWIND3).init(_phi0(40, 32, 0))
+    with pytest.raises(lib.DugksError):
+        b.set(0, t2, 5)
+    b2 = Batch(2, lib.F64, lib.UPWIND3, 0)
+    t3 = Solver(40, 32, 0.02, 4.0, 0.5, recon=lib.UPWIND3, scheme=lib.T3S3).init(_phi0(40, 32, 0))
+    with pytest.raises(lib.DugksError):
+        b2.set(0, t3, 5)
