@@ -129,7 +129,7 @@ def copy_bandwidth():
 
 def _profile_record(name: str, tile_rows: int):
     """A committed rocprofv3 PMC summary (profiles/<name>.json) if it was taken
-    with the kernel sources of this build and the same tile height (the halo
+    with the current kernel sources and the same tile height (the halo
     rows re-read depend on it), else None."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name + ".json")
     if not os.path.exists(path):
@@ -148,7 +148,7 @@ def _profile_record(name: str, tile_rows: int):
 
 def profiled_tile_rows(name: str):
     """The tile height a committed PMC summary was taken at, when it matches
-    the kernel sources of this build: the autotuner's pick for this kernel
+    the current kernel sources: the autotuner's pick for this kernel
     version, reused (a tuning cache), so that the run and its traffic figure
     describe the same launches.  None: tune."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", name + ".json")
@@ -348,7 +348,7 @@ def cpu_baseline(w):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -50,7 +50,7 @@ typedef enum {
   DUGKS_ENOMEM = 2,       /* host allocation failed                            */
   DUGKS_EDEVICE = 3,      /* a HIP launch or runtime call failed               */
   DUGKS_ENUMERIC = 4,     /* non-finite total mass                             */
-  DUGKS_EUNSUPPORTED = 5  /* valid request this build does not provide         */
+  DUGKS_EUNSUPPORTED = 5  /* valid request the library does not provide        */
 } dugks_status;
 
 typedef enum { DUGKS_F64 = 0, DUGKS_F32 = 1 } dugks_precision;
@@ -75,7 +75,7 @@ typedef enum { DUGKS_CENTRAL2 = 0, DUGKS_UPWIND3 = 1, DUGKS_CENTRAL4 = 2 } dugks
  *                 X = x / nx, Y = y / ny
  *  DEFORMATION    u = -p0 sin(4 pi x/nx) sin(4 pi y/ny) cos(pi t / p1)
  *                 v = -p0 cos(4 pi x/nx) cos(4 pi y/ny) cos(pi t / p1)  (Eq. 45)
- *  ARRAYS         not provided by this build (DUGKS_EUNSUPPORTED). */
+ *  ARRAYS         not provided by the library (DUGKS_EUNSUPPORTED). */
 typedef enum {
   DUGKS_VEL_UNIFORM = 0,
   DUGKS_VEL_ROTATION = 1,

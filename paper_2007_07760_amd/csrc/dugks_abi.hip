@@ -596,7 +596,7 @@ const char* dugks_strerror(int status) {
     case DUGKS_ENOMEM: return "out of host memory";
     case DUGKS_EDEVICE: return "HIP launch or runtime call failed";
     case DUGKS_ENUMERIC: return "non-finite total mass";
-    case DUGKS_EUNSUPPORTED: return "not supported by this build";
+    case DUGKS_EUNSUPPORTED: return "not supported by this library";
     default: return "unknown status";
   }
 }

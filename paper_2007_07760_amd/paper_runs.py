@@ -89,11 +89,11 @@ def _e_final(c: dict, phi: np.ndarray, phi0: np.ndarray) -> float:
     return e_phi(phi, phi0)
 
 
-def run_alone(configs: list[dict], flags: int = 0) -> list[float | None]:
+def run_alone(cases: list[dict], flags: int = 0) -> list[float | None]:
     """Each configuration on its own (per-step launches); None where the
     scheme does not allow it."""
     out = []
-    for c in configs:
+    for c in cases:
         if not allowed(c):
             out.append(None)
             continue
@@ -107,19 +107,19 @@ def run_alone(configs: list[dict], flags: int = 0) -> list[float | None]:
     return out
 
 
-def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float | None]:
+def run(cases: list[dict], graph_steps: int = 64, flags: int = 0) -> list[float | None]:
     """Run every configuration (one reconstruction, one time scheme) in one
     FP64 batch and return E_phi of each after its own step count; None where
     the scheme does not allow it.  flags: plan flags (DUGKS_FLAG_DTPHIU_ZERO
     drops d(phi u)/dt from the source)."""
-    if not configs:
+    if not cases:
         return []
-    recon = configs[0]["recon"]
-    scheme = configs[0].get("scheme", C.T2)
-    assert all(c["recon"] == recon and c.get("scheme", C.T2) == scheme for c in configs)
-    b = Batch(len(configs), C.F64, recon, C.BATCH_T3S3 if scheme == C.T3S3 else 0)
-    sol, p0 = [None] * len(configs), [None] * len(configs)
-    for k, c in enumerate(configs):
+    recon = cases[0]["recon"]
+    scheme = cases[0].get("scheme", C.T2)
+    assert all(c["recon"] == recon and c.get("scheme", C.T2) == scheme for c in cases)
+    b = Batch(len(cases), C.F64, recon, C.BATCH_T3S3 if scheme == C.T3S3 else 0)
+    sol, p0 = [None] * len(cases), [None] * len(cases)
+    for k, c in enumerate(cases):
         if not allowed(c):
             continue
         phi0 = c["phi0"]()
@@ -129,14 +129,14 @@ def run(configs: list[dict], graph_steps: int = 64, flags: int = 0) -> list[floa
         b.set(k, s, c["steps"])
         sol[k], p0[k] = s, phi0
     b.commit()
-    left = max(c["steps"] for c, s in zip(configs, sol) if s is not None) if any(sol) else 0
+    left = max(c["steps"] for c, s in zip(cases, sol) if s is not None) if any(sol) else 0
     while left > 0:
         chunk = min(left, 20 * graph_steps)
         b.step(chunk, graph_steps=graph_steps)
         left -= chunk
     st = b.sync()
     out = []
-    for k, (s, c, phi0) in enumerate(zip(sol, configs, p0)):
+    for k, (s, c, phi0) in enumerate(zip(sol, cases, p0)):
         if s is None:
             out.append(None)
             continue
