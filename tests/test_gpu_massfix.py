@@ -144,3 +144,24 @@ def test_fp32_full_runs(lib, name, steps, l2_bar, orc):
     print(line, flush=True)
     assert worst <= 1e-9
     assert l2 <= l2_bar
+
+
+def test_fp32_headline_size(lib):
+    """4096^2 FP32 with the fused correction at the tile heights the
+    autotuner picks for it: the same bits at both, relative mass drift
+    <= 1e-9 at every check, and close to the FP64 field after 100 steps."""
+    import torch
+    w = I.workload("h1")
+    a = _solver(lib, w, lib.F32, lib.FLAG_MASS_FIX, tile_rows=32)
+    b = _solver(lib, w, lib.F32, lib.FLAG_MASS_FIX, tile_rows=96)
+    m0 = a.mass0()
+    for _ in range(10):
+        a.step(10)
+        b.step(10)
+        assert abs(a.mass() - m0) / m0 <= 1e-9
+    assert torch.equal(a.distributions(), b.distributions())
+    g64 = _solver(lib, w, lib.F64).step(100)
+    p32 = a.phi().cpu().numpy().astype(np.float64)
+    l2 = _l2(p32, g64.phi().cpu().numpy())
+    print(f"h1 4096^2 100 steps: FP32+fix vs FP64 L2 {l2:.2e}", flush=True)
+    assert l2 <= 2e-6   # measured 4.1e-7

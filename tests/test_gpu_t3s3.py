@@ -93,11 +93,16 @@ def test_t3s3_rejects_large_step(gpu):
 
 
 def test_t3s3_headline_size_two_steps(gpu, orc):
-    """4096^2, 64 circles in rotation, M = 0.02: the full field after two steps."""
+    """4096^2, 64 circles in rotation, M = 0.02: the full field after two
+    steps, at the default tile height and at the autotuner's pick."""
     w = I.workload("h1")
-    g, o = _pair(gpu, orc, w["nx"], w["ny"], 0.02, w["width"], w["cfl"], w["recon"],
-                 w["vel_kind"], w["vel_param"], w["phi0"], twin=False, scheme=1)
-    g.step(2)
-    o.run(2)
-    ef, ep, _ = _check(g, o, "t3s3 h1 step 2")
-    assert ef < TOL64 and ep < TOL64
+    o = None
+    for tile in (0, 96):
+        g, o2 = _pair(gpu, orc, w["nx"], w["ny"], 0.02, w["width"], w["cfl"], w["recon"],
+                      w["vel_kind"], w["vel_param"], w["phi0"], tile_rows=tile, twin=False,
+                      scheme=1)
+        if o is None:
+            o = o2.run(2)
+        g.step(2)
+        ef, ep, _ = _check(g, o, f"t3s3 h1 step 2 tile {tile}")
+        assert ef < TOL64 and ep < TOL64
