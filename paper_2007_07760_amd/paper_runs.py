@@ -198,8 +198,8 @@ def main(argv=None) -> int:
     import argparse
     import json
     import sys
-    ap = argparse.ArgumentParser(description="Run the paper's DUGKS-T2 tables on the GPU and "
-                                 "print E_phi of every entry as JSON.")
+    ap = argparse.ArgumentParser(description="Run the paper's DUGKS tables (T2S2CD, T2S3, "
+                                 "T3S3) on the GPU and print E_phi of every entry as JSON.")
     ap.add_argument("tables", nargs="*", default=["I", "II", "III", "IV", "V", "VIII", "IX"])
     ap.add_argument("--schemes", nargs="*", default=list(SCHEMES))
     args = ap.parse_args(argv)
