@@ -21,8 +21,8 @@ dt < 12 tau = 36 M.
 MLUPS = nx * ny * steps / time / 1e6.  Algorithmic traffic per lattice update:
 f~^n in and f~^{n+1} out (9 + 9 words), phi^{n-1} in and phi^n out (2 words):
 160 B in FP64, 80 B in FP32.  T3S3: stage A reads f^^n and phi^{n-1} (10
-words) and writes f~(t') and Q with the phi plane (20), stage B reads both
-(20) and writes f^^{n+1} (10): 60 words, 480 B in FP64.  Peak HBM bandwidth of
+words) and writes f~(t') with the phi plane and Q (19), stage B reads both
+(19) and writes f^^{n+1} (10): 58 words, 464 B in FP64.  Peak HBM bandwidth of
 MI355X: 8 TB/s.
 """
 from __future__ import annotations
@@ -35,7 +35,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_LU = 20
-WORDS_PER_LU_T3S3 = 60
+WORDS_PER_LU_T3S3 = 58
 T3S3_MOBILITY = 0.02
 CPU_STEPS = 16         # oracle sample: about 10-30 s on the host cores
 

@@ -199,8 +199,9 @@ struct Marcher {
   int lane, col;
   int ocol;                 // owned lanes: column within the strip
   // the strip's own chunk column of the output (rdst), of stage A's second
-  // output Q (rdst2) and of stage B's input Q (raux); the strip's mass partials
-  rsrc_t rdst, rdst2, rpart, raux;
+  // output Q (rdst2), of stage B's input Q (raux) and of the input itself
+  // (rin: stage B reads phi^n there); the strip's mass partials
+  rsrc_t rdst, rdst2, rpart, raux, rin;
   int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
   bool owned;
   int y0, y1, base;
@@ -314,14 +315,16 @@ struct Marcher {
   __device__ __forceinline__ void face_stage(int k) {
     const int L = LPAD + lane;
     const int kk = wrapi(k, a.ny);
-    // stage B: Q of the row (Eq. 32 value), read before the face work so that
-    // its loads are in flight meanwhile; lanes outside the owned columns read
+    // stage B: Q of the row (Eq. 32 value) and phi^n, the history plane of
+    // stage A's f~(t') (the input), read before the face work so that the
+    // loads are in flight meanwhile; lanes outside the owned columns read
     // nothing (out-of-range offsets read 0)
     T qv[10];
     if (STAGE == STAGE_B && upd) {
       const unsigned oq = owned ? (unsigned)((kk * a.CH + ocol) * (int)sizeof(T)) : OFF_NONE;
 #pragma unroll
-      for (int i = 0; i < 10; i++) qv[i] = bload(raux, oq + i * (unsigned)(OWN * sizeof(T)), T(0));
+      for (int i = 0; i < 9; i++) qv[i] = bload(raux, oq + i * (unsigned)(OWN * sizeof(T)), T(0));
+      qv[9] = bload(rin, oq + 9 * (unsigned)(OWN * sizeof(T)), T(0));
     }
     T out[9];
     T phN = T(0), phE = T(0);
@@ -425,8 +428,7 @@ struct Marcher {
           bstore(fma(a.wo1, out[i], fma(a.kap, d, bp)), rdst, ob + i * PL);
           bstore(fma(a.wo2, out[i], fma(-a.kap, d, bp)), rdst2, ob + i * PL);
         }
-        bstore(ph0, rdst, ob + 9 * PL);
-        bstore(ph0, rdst2, ob + 9 * PL);
+        bstore(ph0, rdst, ob + 9 * PL);   // Q needs no history plane: stage B reads this one
       } else {
         // f^^{n+1} = Q + kap (X' - fbar+) + (4/7) dt L**, kap (X' - fbar+)
         // being (3/4) dt (Omega + S) at t'; phi^n goes on as the history
@@ -545,6 +547,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
     m.rdst = make_rsrc(dst + c0, nb);
     m.rdst2 = make_rsrc((STAGE == STAGE_A ? dst2 : dst) + c0, nb);
     m.raux = make_rsrc((STAGE == STAGE_B ? aux : src) + c0, nb);   // used by stage B
+    m.rin = make_rsrc(src + c0, nb);
   }
   m.y0 = seg * a.seg_rows;
   m.y1 = min(m.y0 + a.seg_rows, a.ny);
