@@ -25,7 +25,9 @@
  *    the time t_n = n dt of the velocity field, and the zero d(phi u)/dt of the
  *    first step).
  *  - Layout in the state: a 256-byte header, the face-stencil and velocity
- *    tables, two ping-pong buffers and mass scratch.  A buffer holds the grid
+ *    tables, two ping-pong buffers and mass scratch (T3S3 states: also a
+ *    second stencil table and two stage buffers, f~ at t + dt/3 and Q of
+ *    Eq. 32).  A buffer holds the grid
  *    in strips of 58 columns (the columns one 64-lane wavefront owns); row y
  *    of a strip is one chunk of 10 planes of 58 elements -- f~_0..f~_8 and the
  *    phi of the previous step -- padded to whole 128-byte lines.  Callers read
@@ -138,7 +140,8 @@ void dugks_plan_destroy(dugks_plan *plan);
 size_t dugks_state_bytes(const dugks_plan *plan);
 
 /* Write the first state (step 0) from phi0 (device, FP64, [ny][nx] dense):
- * f~^0 = feq(phi0, u(x, 0)) - (dt/2) S^0 with d(phi u)/dt = 0, and the
+ * f~^0 = feq(phi0, u(x, 0)) - (dt/2) S^0 with d(phi u)/dt = 0 (T2; T3S3
+ * stores f^0 = feq - (dt/4) S^0), i.e. f = feq at t = 0, and the
  * coefficient and velocity tables of the plan, and record M0 = sum phi0 (FP64).
  * Asynchronous on `stream`.  The first call on a plan stages the tables in
  * pinned host memory the plan keeps until dugks_plan_destroy, which must not
