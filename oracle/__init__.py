@@ -1,4 +1,4 @@
-"""FP64 CPU oracle of the D2Q9 DUGKS (T2) step -- test infrastructure only.
+"""FP64 CPU oracle of the D2Q9 DUGKS step (T2 and T3S3) -- test infrastructure only.
 
 Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product library neither imports nor

@@ -1,8 +1,9 @@
 /*
- * dugks_oracle.c -- plain FP64 CPU oracle of one D2Q9 DUGKS (T2) step for the
- * conservative Allen-Cahn equation, written from the paper (arXiv 2007.07760,
- * Sec. II).  TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and
- * the CPU-baseline leg of the benchmark; the product library never touches it.
+ * dugks_oracle.c -- plain FP64 CPU oracle of one D2Q9 DUGKS step (T2, and the
+ * three-level T3S3 of Sec. II.B.2 in t3s3_step) for the conservative
+ * Allen-Cahn equation, written from the paper (arXiv 2007.07760, Sec. II).
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; the product library never touches it.
  *
  * The step takes the paper's operations in order, one full-grid pass each, with
  * every intermediate kept in its own array so that each line can be checked
@@ -17,8 +18,8 @@
  *   8. meso-flux and cell update         Eq. (21), update of the Eq. (15) form with dt
  * Readings of points the paper leaves open (tau = 3 M, phi = sum f, the 1/2 of
  * the Taylor term, the isotropic stencils, the upwind tie, the time
- * discretisation of d(phi u)/dt, the first state) are listed in the design notes
- * and repeated at the place they are used below.
+ * discretisation of d(phi u)/dt, the first state) are stated at the place they
+ * are used below.
  *
  * Built with -ffp-contract=off so that each expression rounds as written.
  */
