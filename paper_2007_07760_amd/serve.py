@@ -7,8 +7,8 @@ its phi0 in device memory, and attaches it to one batch (include/dugks.h:
 one persistent kernel per step over every active grid, K-step hipGraph
 replays).  Grids leave the batch when they reach their own step count; their
 phi is copied to pinned host memory and the request completes when the copy
-has landed.  Requests that arrive while others are on the GPU join at the
-next round.  The baseline runs the same requests one at a time, in arrival
+has landed.  Requests that arrive while others are on the GPU join before
+the next group of K steps.  The baseline runs the same requests one at a time, in arrival
 order, each with its own per-step launches (dugks_step).
 
 Host-side scheduling only: every step of every solve runs in libdugks.so.
