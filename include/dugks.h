@@ -109,7 +109,9 @@ typedef enum { DUGKS_T2 = 0, DUGKS_T3S3 = 1 } dugks_scheme;
  * each f~_i of those cells as it loads it.  dugks_phi, dugks_distributions
  * and dugks_mass include the pending correction.  Segments of such plans are
  * whole 8-row groups (tile_rows is rounded up), so results stay independent
- * of the tiling. */
+ * of the tiling.  T3S3 plans take it in the same way on their stored f^:
+ * stage A applies the pending correction as it reads f^^n, stage B sums
+ * f^^{n+1}. */
 #define DUGKS_FLAG_MASS_FIX 2u
 
 typedef struct {
@@ -131,8 +133,7 @@ typedef struct dugks_plan dugks_plan;
 /* Validate p and build an immutable plan (stencil coefficients of the chosen
  * reconstruction, collision coefficients, launch geometry).  Host-only: no HIP
  * call is made.  Errors: EINVAL (p or out NULL, a field out of range, T3S3
- * with dt >= 12 tau), EUNSUPPORTED (ARRAYS velocity; T3S3 with
- * DUGKS_FLAG_MASS_FIX), ENOMEM. */
+ * with dt >= 12 tau), EUNSUPPORTED (ARRAYS velocity), ENOMEM. */
 int dugks_plan_create(const dugks_params *p, dugks_plan **out);
 void dugks_plan_destroy(dugks_plan *plan);
 
@@ -234,8 +235,7 @@ typedef struct dugks_batch dugks_batch;
 /* Create a batch of `capacity` slots (1..65536), all empty.  flags: 0,
  * DUGKS_FLAG_MASS_FIX (then every attached plan must carry it, else none may)
  * or DUGKS_BATCH_T3S3 (then every attached plan is a T3S3 plan).  Errors:
- * EINVAL, EUNSUPPORTED (DUGKS_FLAG_MASS_FIX with DUGKS_BATCH_T3S3), ENOMEM,
- * EDEVICE. */
+ * EINVAL, ENOMEM, EDEVICE. */
 int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon,
                        uint32_t flags, dugks_batch **out);
 /* Wait for the device, then free the batch and its device memory. */

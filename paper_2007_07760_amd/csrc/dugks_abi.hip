@@ -195,7 +195,6 @@ int validate(const dugks_params* p) {
       !(p->vel_param[1] > 0.0))
     return DUGKS_EINVAL;
   if (p->vel_kind == DUGKS_VEL_ARRAYS) return DUGKS_EUNSUPPORTED;
-  if (p->scheme == DUGKS_T3S3 && (p->flags & DUGKS_FLAG_MASS_FIX)) return DUGKS_EUNSUPPORTED;
   return DUGKS_OK;
 }
 
@@ -264,6 +263,12 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s, boo
 template <typename T>
 int launch_step(const dugks_plan* P, void* state, int64_t n, hipStream_t s, bool fix = true) {
   if (P->p.scheme == DUGKS_T3S3) {
+    // with the fused correction, stage A applies the pending one as it reads
+    // f^^n and stage B gives the partials of f^^{n+1}: one reduction per step
+    if (P->p.flags & DUGKS_FLAG_MASS_FIX) {
+      int rc = launch_stage<T, true, STAGE_A>(P, state, n, s, false);
+      return rc ? rc : launch_stage<T, true, STAGE_B>(P, state, n, s, fix);
+    }
     int rc = launch_stage<T, false, STAGE_A>(P, state, n, s);
     return rc ? rc : launch_stage<T, false, STAGE_B>(P, state, n, s);
   }

@@ -198,9 +198,9 @@ template <typename T, int R, bool MFIX>
 int launch_batch_step(dugks_batch* B, hipStream_t s, bool finish) {
   const GridDesc<T>* desc = static_cast<const GridDesc<T>*>(B->d_desc);
   if (B->scheme == DUGKS_T3S3) {   // the two stages over every tile, in turn
-    hipLaunchKernelGGL((batch_step_kernel<T, R, false, STAGE_A>), dim3(B->grid_blocks),
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_A>), dim3(B->grid_blocks),
                        dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
-    hipLaunchKernelGGL((batch_step_kernel<T, R, false, STAGE_B>), dim3(B->grid_blocks),
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_B>), dim3(B->grid_blocks),
                        dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
   } else {
     hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
@@ -239,10 +239,10 @@ int occupancy(int* per_cu, int scheme) {
   if (scheme == DUGKS_T3S3) {   // the smaller of the two stages' residencies
     int a = 0, b = 0;
     int rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &a, reinterpret_cast<const void*>(&batch_step_kernel<T, R, false, STAGE_A>), LANES, 0));
+        &a, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_A>), LANES, 0));
     if (!rc)
       rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &b, reinterpret_cast<const void*>(&batch_step_kernel<T, R, false, STAGE_B>), LANES,
+          &b, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_B>), LANES,
           0));
     *per_cu = std::min(a, b);
     return rc;
@@ -330,7 +330,6 @@ int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint3
   if (capacity < 1 || capacity > 65536 || precision < 0 || precision > 1 || recon < 0 ||
       recon > 2 || (flags & ~(DUGKS_FLAG_MASS_FIX | DUGKS_BATCH_T3S3)))
     return DUGKS_EINVAL;
-  if ((flags & DUGKS_FLAG_MASS_FIX) && (flags & DUGKS_BATCH_T3S3)) return DUGKS_EUNSUPPORTED;
   dugks_batch* B = new (std::nothrow) dugks_batch();
   if (!B) return DUGKS_ENOMEM;
   B->cap = capacity;

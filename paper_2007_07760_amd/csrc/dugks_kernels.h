@@ -189,6 +189,11 @@ __device__ __forceinline__ T over_norm(T num, T gx, T gy) {
 template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
+  // the fused mass correction: the stored state's loads take the pending
+  // correction (T2; T3S3 stage A, which reads f^^n), the state's writes give
+  // the new mass partials (T2; stage B, which writes f^^{n+1})
+  static constexpr bool FIX_LOAD = MFIX && STAGE != STAGE_B;
+  static constexpr bool FIX_SUM = MFIX && STAGE != STAGE_A;
 
   const StepArgs<T>& a;
   const T* __restrict__ src;
@@ -239,7 +244,7 @@ struct Marcher {
     const T* p = row_src(wrapi(row, a.ny));
 #pragma unroll
     for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
-    if (MFIX) {
+    if (FIX_LOAD) {
       const bool fit = d.f[0] < fitmax;
 #pragma unroll
       for (int i = 0; i < 9; i++) d.f[i] = fit ? d.f[i] + cw(i) : d.f[i];
@@ -412,7 +417,7 @@ struct Marcher {
           const T tfp = fma(a.kap, x[i] - bp, bp);
           const T v = tfp + out[i];
           bstore(v, rdst, ob + i * PL);
-          if (MFIX) {
+          if (FIX_SUM) {
             cs += owned ? (double)v : 0.0;
             if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
           }
@@ -435,12 +440,17 @@ struct Marcher {
 #pragma unroll
         for (int i = 0; i < 9; i++) {
           const T bp = bfp[slotB(k)][i][L];
-          bstore(fma(a.wo1, out[i], fma(a.kap, x[i] - bp, qv[i])), rdst, ob + i * PL);
+          const T v = fma(a.wo1, out[i], fma(a.kap, x[i] - bp, qv[i]));
+          bstore(v, rdst, ob + i * PL);
+          if (FIX_SUM) {
+            cs += owned ? (double)v : 0.0;
+            if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
+          }
         }
         bstore(qv[9], rdst, ob + 9 * PL);
       }
     }
-    if (MFIX) {
+    if (FIX_SUM) {
       // phi^{n+1} of the row into the group total; a group never straddles
       // two segments (segments are whole groups), so its sum -- lanes in a
       // fixed butterfly after rows in order -- does not depend on the tiling

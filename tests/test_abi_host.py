@@ -110,8 +110,6 @@ def test_calls_reject_null_before_the_device(lib):
         out = __import__("ctypes").c_void_p()
         assert lib.dugks_batch_create(0, 0, 0, 0, __import__("ctypes").byref(out)) == C.EINVAL
         assert lib.dugks_batch_create(4, 0, 0, 8, __import__("ctypes").byref(out)) == C.EINVAL
-        assert lib.dugks_batch_create(4, 0, 1, C.FLAG_MASS_FIX | C.BATCH_T3S3,
-                                      __import__("ctypes").byref(out)) == C.EUNSUPPORTED
     finally:
         C.dugks_plan_destroy(plan)
 
@@ -200,7 +198,7 @@ def test_plan_t3s3_validation(lib):
     assert C.dugks_plan_create_status(_p(mobility=0.01, cfl=0.5, scheme=1)) == C.EINVAL
     assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.5, scheme=2)) == C.EINVAL
     assert C.dugks_plan_create_status(_p(mobility=0.02, cfl=0.5, scheme=1,
-                                         flags=C.FLAG_MASS_FIX)) == C.EUNSUPPORTED
+                                         flags=C.FLAG_MASS_FIX)) == C.OK
     a = C.dugks_plan_create(_p(mobility=0.02, cfl=0.5))
     b = C.dugks_plan_create(_p(mobility=0.02, cfl=0.5, scheme=1))
     try:

@@ -168,11 +168,12 @@ def test_empty_batch_and_cleared_slots(lib):
     assert torch.equal(frozen, ref.distributions())
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_t3s3_batch_equals_alone(lib, precision):
+@pytest.mark.parametrize("precision,flags", [(0, 0), (1, 0), (1, 2)])
+def test_t3s3_batch_equals_alone(lib, precision, flags):
     """DUGKS-T3S3 grids in a DUGKS_BATCH_T3S3 batch (stage A and stage B
     kernels over all grids per batch step, graph replays) equal their alone
-    runs bitwise, with targets that stop grids at different steps."""
+    runs bitwise, with targets that stop grids at different steps; FP32 also
+    with the fused mass correction."""
     import torch
     from paper_2007_07760_amd.batch import Batch
     from paper_2007_07760_amd.solver import Solver
@@ -180,10 +181,11 @@ def test_t3s3_batch_equals_alone(lib, precision):
     def make(k, g):
         nx, ny, kind, prm = g
         return Solver(nx, ny, 0.02, 4.0, 0.5, recon=lib.UPWIND3, precision=precision,
-                      vel_kind=kind, vel_param=prm, scheme=lib.T3S3).init(_phi0(nx, ny, k))
+                      vel_kind=kind, vel_param=prm, flags=flags,
+                      scheme=lib.T3S3).init(_phi0(nx, ny, k))
 
-    print(f"case T3S3 batch precision={precision}", flush=True)
-    b = Batch(len(GRIDS), precision, lib.UPWIND3, lib.BATCH_T3S3)
+    print(f"case T3S3 batch precision={precision} flags={flags}", flush=True)
+    b = Batch(len(GRIDS), precision, lib.UPWIND3, lib.BATCH_T3S3 | flags)
     targets = [9 + 3 * k for k in range(len(GRIDS))]
     sol = []
     for k, g in enumerate(GRIDS):
