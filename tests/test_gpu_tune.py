@@ -23,6 +23,7 @@ def lib():
     (0, 0, 0, 0.005),   # FP64 T2
     (1, 2, 0, 0.005),   # FP32 with the fused mass correction
     (0, 0, 1, 0.02),    # FP64 T3S3 (dt < 12 tau)
+    (1, 2, 1, 0.02),    # FP32 T3S3 with the fused mass correction
 ])
 def test_tune_keeps_state_and_results(lib, precision, flags, scheme, mobility):
     import torch
