@@ -150,7 +150,9 @@ def test_t3s3_mass_fix_ragged(gpu, recon):
     g64 = make().step(80)
     d = float(np.max(np.abs(fixed[0].phi().cpu().numpy() - g64.phi().cpu().numpy())))
     print(f"t3s3 ragged recon {recon}: FP32+fix vs FP64 phi L-inf {d:.2e}", flush=True)
-    assert d < 1e-4
+    # measured 8.3e-5 (central-2, which amplifies rounding most), 5.8e-6
+    # (upwind-3), 2.2e-6 (central-4)
+    assert d < 3e-4
 
 
 def test_t3s3_rejects_large_step(gpu):
