@@ -203,12 +203,27 @@ def bench_t3s3(w, steps, warmup, tile_rows):
     achieved = WORDS_PER_LU_T3S3 * 8 * lus / (k_ms * 1e-3) / 1e9
     del s
     torch.cuda.empty_cache()
+    # the FP32 form of the same step, with the fused mass correction
+    s = Solver(w["nx"], w["ny"], T3S3_MOBILITY, w["width"], w["cfl"], recon=w["recon"],
+               precision=C.F32, vel_kind=w["vel_kind"], vel_param=w["vel_param"],
+               flags=C.FLAG_MASS_FIX, scheme=C.T3S3).init(w["phi0"])
+    rows32, source32 = s.tune(), "tuned"
+    _, ev32 = time_steps(s, steps, warmup)
+    m0 = s.mass0()
+    drift = abs(s.mass() - m0) / m0
+    del s
+    torch.cuda.empty_cache()
     return {"value": round(lus * steps / (ev_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(ev_ms / steps, 4), "dtype": "f64",
             "mobility": T3S3_MOBILITY, "kernels": "step_kernel stage A + stage B",
             "step_kernels_ms": round(k_ms, 4), "achieved": round(achieved, 1),
             "frac": round(achieved / HBM_PEAK_GBS, 4), "tile_rows": rows, "tile_source": source,
-            "traffic": profile_traffic_t3s3(rows), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8}
+            "traffic": profile_traffic_t3s3(rows), "bytes_per_lu": WORDS_PER_LU_T3S3 * 8,
+            "fp32": {"value": round(lus * steps / (ev32 * 1e-3) / 1e6, 1), "unit": "MLUPS",
+                     "ms_per_step": round(ev32 / steps, 4), "dtype": "f32",
+                     "mass_correction": "fused, every step",
+                     "relative_mass_drift": float(f"{drift:.3g}"), "tile_rows": rows32,
+                     "tile_source": source32, "bytes_per_lu": WORDS_PER_LU_T3S3 * 4}}
 
 
 def bench_shard_share(w, steps, warmup):
