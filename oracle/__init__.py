@@ -30,7 +30,7 @@ _LIBS = {"plain": os.path.join(_HERE, "libdugks_oracle.so"),
 _FLAGS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]}
 _LIB = _LIBS["plain"]
 
-CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
+CENTRAL2, UPWIND3, CENTRAL4, UPWIND5 = 0, 1, 2, 3   # UPWIND5: T2S5 (oracle only)
 T2, T3S3 = 0, 1
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
 

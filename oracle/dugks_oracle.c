@@ -18,8 +18,13 @@
  *   8. meso-flux and cell update         Eq. (21), update of the Eq. (15) form with dt
  * Readings of points the paper leaves open (tau = 3 M, phi = sum f, the 1/2 of
  * the Taylor term, the isotropic stencils, the upwind tie, the time
- * discretisation of d(phi u)/dt, the first state) are stated at the place they
- * are used below.
+ * discretisation of d(phi u)/dt, the first state, the fifth-order stencil of
+ * T2S5) are stated at the place they are used below.
+ *
+ * The fifth-order reconstruction (ORC_UPWIND5, for T2S5) is a reading: the
+ * paper gives no stencil.  It is pinned by exactness and error identities of
+ * the interpolation, not by the paper's numbers (parity with the authors'
+ * stencil unpinned); no GPU kernel implements it.
  *
  * Built with -ffp-contract=off so that each expression rounds as written.
  */
@@ -251,12 +256,48 @@ static inline double at_nt(const oracle_params *p, const double *a, int x,
                wrap(y + s * ndy + t * tdy, p->ny))];
 }
 
+/* Lagrange weights w[j - m0] of the nodes j = m0..m1 (unit spacing) for the
+ * value at coordinate c: w_j = prod_{k != j} (c - k) / (j - k). */
+static void lagrange(int m0, int m1, double c, double *w) {
+  for (int j = m0; j <= m1; j++) {
+    double v = 1.0;
+    for (int k = m0; k <= m1; k++)
+      if (k != j) v *= (c - k) / (double)(j - k);
+    w[j - m0] = v;
+  }
+}
+
 /* One face value bf_i for the face between L = (x, y) and R = L + (ndx, ndy). */
 static double face_value(const oracle_params *p, const deriv_planes *d, int i,
                          int x, int y, int ndx, int ndy, double h) {
   const double *a = d->f;
   int en = EX[i] * ndx + EY[i] * ndy;   /* xi_i . normal  */
   int et = EX[i] * ndy + EY[i] * ndx;   /* xi_i . tangent */
+  if (p->recon == ORC_UPWIND5) {
+    /* T2S5 (Sec. III names a fifth-order, non-isotropic reconstruction and
+     * gives no stencil; reading): fbar+ at the foot x_b - xi_i h by a
+     * tensor product of one-dimensional Lagrange interpolations in cell-centre
+     * coordinates measured from L.  Along the normal the foot lies at
+     * 1/2 - en h: five cells centred on the upstream cell (L for en > 0, R
+     * for en < 0), or, with the foot on the face (en = 0), the six cells
+     * centred on the face.  Along the tangent it lies at -et h: the five
+     * cells centred on the row of L, or that row alone when et = 0.  Exact
+     * for polynomials of degree <= 4 in each coordinate. */
+    int n0 = -2, n1 = 3;                  /* en = 0 */
+    if (en > 0) n1 = 2;                   /* cells L-2 .. L+2 */
+    if (en < 0) n0 = -1;                  /* cells R-2 .. R+2 */
+    int t0 = et != 0 ? -2 : 0, t1 = et != 0 ? 2 : 0;
+    double wn[6], wt[5];
+    lagrange(n0, n1, 0.5 - en * h, wn);
+    lagrange(t0, t1, -et * h, wt);
+    double v = 0.0;
+    for (int s = n0; s <= n1; s++) {
+      double row = 0.0;
+      for (int t = t0; t <= t1; t++) row += wt[t - t0] * at_nt(p, a, x, y, ndx, ndy, s, t);
+      v += wn[s - n0] * row;
+    }
+    return v;
+  }
   if (p->recon == ORC_UPWIND3) {
     /* face centre x_b and foot of the characteristic x_b - xi_i h */
     double bx = x + 0.5 + 0.5 * ndx, by = y + 0.5 + 0.5 * ndy;

@@ -19,7 +19,7 @@
 extern "C" {
 #endif
 
-enum { ORC_CENTRAL2 = 0, ORC_UPWIND3 = 1, ORC_CENTRAL4 = 2 };
+enum { ORC_CENTRAL2 = 0, ORC_UPWIND3 = 1, ORC_CENTRAL4 = 2, ORC_UPWIND5 = 3 };
 enum { ORC_T2 = 0, ORC_T3S3 = 1 };
 enum { ORC_VEL_UNIFORM = 0, ORC_VEL_ROTATION = 1, ORC_VEL_SINGLE_VORTEX = 2,
        ORC_VEL_DEFORMATION = 3, ORC_VEL_ARRAYS = 4 };
