@@ -4,7 +4,9 @@ accepts and rejects what the header says; entry points reject bad arguments
 before touching the device; the serving pool allocator and the seeded input
 generators behave as documented."""
 import math
+import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -207,3 +209,13 @@ def test_plan_t3s3_validation(lib):
     finally:
         C.dugks_plan_destroy(a)
         C.dugks_plan_destroy(b)
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark measures one GPU; asked for more it exits with a message
+    before touching a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
