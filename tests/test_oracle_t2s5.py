@@ -13,12 +13,16 @@ applies), the fifth-order error on a smooth field, and the step's invariants
 with this reconstruction.  Parity of a GPU kernel with it is not claimed: no
 kernel implements it.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 from paper_2007_07760_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_translation_n128.json")
 
 EX = [0, 1, 1, 0, -1, -1, -1, 0, 1]
 EY = [0, 0, 1, 1, 1, 0, -1, -1, -1]
@@ -158,3 +162,21 @@ def test_fourier_mode_decay_and_phase(orc):
     shift = (-np.angle(A)) % (2 * math.pi)
     want = (k * ux * t) % (2 * math.pi)
     assert abs(shift - want) < 1e-3 * k * ux * t
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("DUGKS_SLOW") != "1",
+                    reason="about 10 minutes on 8 cores; DUGKS_SLOW=1 runs it")
+def test_table1_translation_n128_comparison(orc):
+    """Table I, DUGKS-T2S5, N = 128, Pe = 128, Cn = 1/32, M = 0.02, C = 0.8:
+    5.04e-3 printed, the oracle's reading gives 5.16e-3 (and 4.66e-3 against
+    4.53e-3 at C = 0.5).  The stencil is a reading, so this compares rather
+    than pins: within 5 %, as the other schemes' readings reproduce theirs."""
+    rows = json.load(open(GOLDEN))["rows"]
+    want = next(r["E_phi"] for r in rows if r["scheme"] == "T2S5" and r["cfl"] == 0.8)
+    n, m = 128, 0.02
+    u0 = 128 * m / n
+    phi0 = I.tanh_circle(n, n, n / 2, n / 2, n / 5, n / 32)
+    p = orc.Params(n, n, m, n / 32, 0.8, orc.UPWIND5, orc.VEL_UNIFORM, (u0, u0))
+    s = orc.State(p, phi0).run(int(round(n / u0 / 0.8)))
+    assert orc.e_phi(s.phi(), phi0) == pytest.approx(want, rel=0.05)
