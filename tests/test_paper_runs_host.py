@@ -27,6 +27,8 @@ def test_empty_entries_are_the_disallowed_ones(table):
         _, cf = P.table_configs(table, scheme)
         assert all(P.allowed(c) for c in cf)
         assert all(v is not None for row in g[scheme].values() for v in row)
+    # T2S5 is a two-level scheme too: the paper prints every entry
+    assert all(len(row) == len(cols) and None not in row for row in g["T2S5"].values())
 
 
 @pytest.mark.parametrize("table", TABLES)
