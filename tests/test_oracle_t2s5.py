@@ -166,7 +166,7 @@ def test_fourier_mode_decay_and_phase(orc):
 
 @pytest.mark.slow
 @pytest.mark.skipif(os.environ.get("DUGKS_SLOW") != "1",
-                    reason="about 10 minutes on 8 cores; DUGKS_SLOW=1 runs it")
+                    reason="1-2 minutes on 8 cores; DUGKS_SLOW=1 runs it")
 def test_table1_translation_n128_comparison(orc):
     """Table I, DUGKS-T2S5, N = 128, Pe = 128, Cn = 1/32, M = 0.02, C = 0.8:
     5.04e-3 printed, the oracle's reading gives 5.16e-3 (and 4.66e-3 against
