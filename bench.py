@@ -37,7 +37,10 @@ HBM_PEAK_GBS = 8000.0
 WORDS_PER_LU = 20
 WORDS_PER_LU_T3S3 = 58
 T3S3_MOBILITY = 0.02
-CPU_STEPS = 16         # oracle sample: about 10-30 s on the host cores
+CPU_STEPS = 16         # oracle sample of the headline grid: about 10-20 s on the host cores
+# steps run before any timed region whatever --warmup says: the GPU's clocks
+# ramp up over the first ~20 steps after idle (690 -> 636 us per FP64 step)
+CLOCK_WARMUP_STEPS = 50
 
 
 def parse():
@@ -67,10 +70,11 @@ def parse():
 
 
 def time_steps(solver, steps, warmup):
-    """Warm up, then time exactly `steps` steps with HIP events on the stream
-    the kernels run on; returns (seconds, ms of the timed region)."""
+    """Warm up (CLOCK_WARMUP_STEPS, then `warmup` more), then time exactly
+    `steps` steps with HIP events on the stream the kernels run on; returns
+    (seconds, ms of the timed region)."""
     import torch
-    for k in range(warmup):
+    for k in range(CLOCK_WARMUP_STEPS + warmup):
         solver.step(1)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -344,20 +348,45 @@ def bench_serving(count):
             "unsaturated": dict(r4(unsat), rate_per_s=round(rate, 1))}
 
 
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w):
-    """The FP64 oracle as it stands, on this host's cores, on a bounded sample of
-    the same workload: its first CPU_STEPS steps on the full 4096^2 grid."""
+    """The FP64 oracle as it stands, on this host's cores, on bounded samples
+    of the measured workloads: the first CPU_STEPS steps of the 4096^2 grid
+    (the `value`, the same workload as the GPU line) and the first steps of the
+    64^2, 256^2 and 512^2 cases."""
     import oracle
-    p = oracle.Params(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
-                      w["recon"], w["vel_kind"], w["vel_param"])
-    s = oracle.State(p, w["phi0"])
-    t0 = time.perf_counter()
-    s.run(CPU_STEPS)
-    dt = time.perf_counter() - t0
-    return {"value": w["nx"] * w["ny"] * CPU_STEPS / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{CPU_STEPS} steps (n=0..{CPU_STEPS - 1}) of the {w['nx']}x{w['ny']} workload, FP64, "
-                      f"{dt:.1f} s"}
+    from paper_2007_07760_amd import inputs as I
+
+    def sample(wl, steps):
+        p = oracle.Params(wl["nx"], wl["ny"], wl["mobility"], wl["width"], wl["cfl"],
+                          wl["recon"], wl["vel_kind"], wl["vel_param"])
+        s = oracle.State(p, wl["phi0"])
+        t0 = time.perf_counter()
+        s.run(steps)
+        dt = time.perf_counter() - t0
+        return wl["nx"] * wl["ny"] * steps / dt / 1e6, dt
+
+    others = {}
+    for name, steps in (("c1", 400), ("c2", 100), ("c3_512", 24)):
+        wl = I.workload(name)
+        v, dt = sample(wl, steps)
+        others[f"{name} {wl['nx']}x{wl['ny']}, {steps} steps"] = {
+            "mlups": round(v, 2), "seconds": round(dt, 2)}
+    v, dt = sample(w, CPU_STEPS)
+    return {"value": round(v, 2), "unit": "MLUPS",
+            "cores": oracle.threads(), "cpu": _cpu_model(), "kind": "oracle",
+            "sample": f"{CPU_STEPS} steps (n=0..{CPU_STEPS - 1}) of the {w['nx']}x{w['ny']} "
+                      f"workload, FP64, {dt:.1f} s",
+            "other_samples": others}
 
 
 def main():
@@ -403,7 +432,8 @@ def main():
         results[prec_name] = dict(
             wall=wall, ev_ms=ev_ms, kernel_ms=k_ms, achieved=achieved,
             mlups=lus * args.steps / (ev_ms * 1e-3) / 1e6, tile_rows=rows, tile_source=source,
-            traffic=profile_traffic(prec_name, rows))
+            traffic=profile_traffic(prec_name, rows), step=s.step_index,
+            phi=s.phi().double().cpu().numpy(), mass0=s.mass0(), mass=s.mass())
         del s
         torch.cuda.empty_cache()
     copy_gbs = copy_bandwidth()
@@ -435,10 +465,19 @@ def main():
                      "kernel_ms": round(r["kernel_ms"], 4),
                      "bytes_per_lu": WORDS_PER_LU * (8 if head == "f64" else 4)},
         "copy_bandwidth_gbs": round(copy_gbs, 1),
+        "clock_warmup_steps": CLOCK_WARMUP_STEPS,
     }
     if "f32" in results and head != "f32":
         f = results["f32"]
+        import numpy as np
+        d = results["f32"]["phi"] - r["phi"]
+        acc = {"step": f["step"],
+               "l2": float(f"{np.sqrt((d * d).sum() / (r['phi'] ** 2).sum()):.3g}"),
+               "linf": float(f"{np.abs(d).max():.3g}"),
+               "relative_mass_drift": float(f"{abs(f['mass'] - f['mass0']) / f['mass0']:.3g}")}
+        assert f["step"] == r["step"]
         line["fp32"] = {"value": round(f["mlups"], 1), "unit": "MLUPS",
+                        "vs_fp64": acc,
                         "ms_per_step": round(f["ev_ms"] / args.steps, 4),
                         "mass_correction": "fused, every step",
                         "kernel_ms": round(f["kernel_ms"], 4),

@@ -35,6 +35,15 @@
  *  - Plans are immutable after creation and may be shared between threads;
  *    calls on distinct states may run concurrently on distinct streams.
  *    Calls on one state must be ordered by the caller.
+ *  - Blow-up (Eq. 39's scheme is only conditionally stable): every state
+ *    carries a sticky status word, DUGKS_OK until a total mass computed for
+ *    it is non-finite -- its phi0 at dugks_init, a dugks_mass call, or the
+ *    per-step sum of plans with DUGKS_FLAG_MASS_FIX -- and DUGKS_ENUMERIC from
+ *    then on.  Launches are asynchronous, so the status is read back with
+ *    dugks_state_status (dugks_batch_status for the slots of a batch).
+ *  - Reading of Eq. (2) where grad(phi) vanishes: n = g / sqrt(|g|^2 + 1e-8),
+ *    g the isotropic gradient -- n = g/|g| to within (1e-4/|g|)^2 / 2 on an
+ *    interface, continuous where g passes through 0.
  */
 #ifndef DUGKS_H
 #define DUGKS_H
@@ -77,7 +86,11 @@ typedef enum { DUGKS_CENTRAL2 = 0, DUGKS_UPWIND3 = 1, DUGKS_CENTRAL4 = 2 } dugks
  *                 X = x / nx, Y = y / ny
  *  DEFORMATION    u = -p0 sin(4 pi x/nx) sin(4 pi y/ny) cos(pi t / p1)
  *                 v = -p0 cos(4 pi x/nx) cos(4 pi y/ny) cos(pi t / p1)  (Eq. 45)
- *  ARRAYS         not provided by the library (DUGKS_EUNSUPPORTED). */
+ *  ARRAYS         a steady field given at the cell centres by the caller
+ *                 (the general prescribed field of Sec. III): u and v arrays
+ *                 passed to dugks_init; the velocity of a face is the mean
+ *                 of its two cells'.  vel_param is unused.  Single grids only
+ *                 (batches refuse such plans: DUGKS_EUNSUPPORTED). */
 typedef enum {
   DUGKS_VEL_UNIFORM = 0,
   DUGKS_VEL_ROTATION = 1,
@@ -133,23 +146,29 @@ typedef struct dugks_plan dugks_plan;
 /* Validate p and build an immutable plan (stencil coefficients of the chosen
  * reconstruction, collision coefficients, launch geometry).  Host-only: no HIP
  * call is made.  Errors: EINVAL (p or out NULL, a field out of range, T3S3
- * with dt >= 12 tau), EUNSUPPORTED (ARRAYS velocity), ENOMEM. */
+ * with dt >= 12 tau), ENOMEM. */
 int dugks_plan_create(const dugks_params *p, dugks_plan **out);
 void dugks_plan_destroy(dugks_plan *plan);
 
-/* Bytes of device memory one state needs (caller allocates, 256-B aligned). */
+/* Bytes of device memory one state needs (caller allocates, 256-B aligned);
+ * ARRAYS plans include a copy of the two velocity planes. */
 size_t dugks_state_bytes(const dugks_plan *plan);
 
 /* Write the first state (step 0) from phi0 (device, FP64, [ny][nx] dense):
  * f~^0 = feq(phi0, u(x, 0)) - (dt/2) S^0 with d(phi u)/dt = 0 (T2; T3S3
  * stores f^0 = feq - (dt/4) S^0), i.e. f = feq at t = 0, and the
- * coefficient and velocity tables of the plan, and record M0 = sum phi0 (FP64).
+ * coefficient and velocity tables of the plan, and record M0 = sum phi0 (FP64;
+ * a non-finite M0 sets the status to DUGKS_ENUMERIC).
+ * uv_dev: ARRAYS plans only (ignored otherwise, may be NULL): the cell
+ * velocities, device, FP64, [2][ny][nx] dense (u plane, then v plane); they
+ * are copied into the state (in the plan's precision) on `stream`, so the
+ * caller may release them once that copy has run.
  * Asynchronous on `stream`.  The first call on a plan stages the tables in
  * pinned host memory the plan keeps until dugks_plan_destroy, which must not
- * run before the copy has executed.  Errors: EINVAL (NULL, misaligned state),
- * EDEVICE. */
+ * run before the copy has executed.  Errors: EINVAL (NULL, misaligned state,
+ * uv_dev NULL for an ARRAYS plan), EDEVICE. */
 int dugks_init(const dugks_plan *plan, void *state, const double *phi0_dev,
-               void *stream);
+               const double *uv_dev, void *stream);
 
 /* Advance the state from step `step` by `nsteps` steps of the plan's scheme:
  * T2 (Eqs. 21-28 with the Eq. 15 update form) is one fused
@@ -187,10 +206,24 @@ int dugks_phi(const dugks_plan *plan, const void *state, int64_t step,
 int dugks_distributions(const dugks_plan *plan, const void *state, int64_t step,
                         void *out_dev, void *stream);
 
+/* The phi history plane of the state at `step` -- phi^{n-1} = sum_i of the
+ * stored distributions one step earlier, the earlier phi of d(phi u)/dt in
+ * Eq. (14b) -- as stored, [ny][nx] dense elements of the plan's precision.
+ * With dugks_distributions it gives the complete input of the next step.
+ * Asynchronous.  Errors: EINVAL, EDEVICE. */
+int dugks_history(const dugks_plan *plan, const void *state, int64_t step,
+                  void *out_dev, void *stream);
+
+/* The state's sticky status word (DUGKS_OK, or DUGKS_ENUMERIC once a total
+ * mass computed for it was non-finite), copied to *status_out (device or
+ * pinned host memory), asynchronously on `stream`.  Errors: EINVAL, EDEVICE. */
+int dugks_state_status(const dugks_plan *plan, const void *state, int32_t *status_out,
+                       void *stream);
+
 /* Total mass sum(phi) of the state at `step`, FP64, Neumaier-compensated, with
  * a fixed reduction order (deterministic), written to *mass_out_dev (device).
- * Uses the state's scratch.  Asynchronous; the caller checks the value it
- * reads back (a non-finite total means the state has blown up).
+ * Uses the state's scratch.  Asynchronous; a non-finite total (the state has
+ * blown up) also sets the state's status to DUGKS_ENUMERIC (dugks_state_status).
  * Errors: EINVAL, EDEVICE. */
 int dugks_mass(const dugks_plan *plan, void *state, int64_t step,
                double *mass_out_dev, void *stream);
@@ -225,6 +258,10 @@ int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
  *    dugks_batch_step.  States must stay allocated while a slot holds them.
  *  - The step counters are the batch's while a state is attached: read them
  *    with dugks_batch_steps.
+ *  - A slot whose state reports DUGKS_ENUMERIC at the end of a batch step
+ *    (non-finite phi0, or a non-finite total in the fused correction of
+ *    DUGKS_FLAG_MASS_FIX batches) stops: its target becomes the step it has
+ *    reached, and dugks_batch_status reports it; other slots go on.
  *  - A batch is not thread-safe; calls on one batch must be serialised. */
 typedef struct dugks_batch dugks_batch;
 
@@ -245,7 +282,7 @@ void dugks_batch_destroy(dugks_batch *batch);
  * to `slot`; the grid advances until its counter reaches `target` (>= step).
  * Replaces whatever the slot held.  Errors: EINVAL (range, NULL, misaligned
  * state, plan of another precision / reconstruction / mass-fix flag / time
- * scheme than the batch's). */
+ * scheme than the batch's), EUNSUPPORTED (an ARRAYS plan). */
 int dugks_batch_set(dugks_batch *batch, int32_t slot, const dugks_plan *plan,
                     void *state, int64_t step, int64_t target);
 /* Empty `slot`.  Errors: EINVAL. */
@@ -265,6 +302,12 @@ int dugks_batch_step(dugks_batch *batch, int64_t nsteps, int32_t graph_steps,
  * (host or device memory; asynchronous on `stream` when `out` is pinned or on
  * the device).  Errors: EINVAL, EDEVICE. */
 int dugks_batch_steps(const dugks_batch *batch, int64_t *out, void *stream);
+/* The status of each slot's state at its last batch step, int32[capacity]
+ * (DUGKS_OK or DUGKS_ENUMERIC; DUGKS_OK for a slot not stepped since it was
+ * set or cleared), copied to `out` (host or device memory; asynchronous on
+ * `stream` when `out` is pinned or on the device).  Errors: EINVAL, EDEVICE. */
+int dugks_batch_status(const dugks_batch *batch, int32_t *out, void *stream);
+
 /* Rows per tile of every grid (a multiple of 8; grids shorter than that are
  * one tile high).  Default 64.  set: EINVAL unless 8 <= rows <= 65536 and
  * rows % 8 == 0; takes effect at the next commit. */

@@ -25,9 +25,14 @@ _SRC = os.path.join(_HERE, "dugks_oracle.c")
 # arithmetic, used to measure how far rounding alone moves the method (the
 # normal grad(phi)/|grad(phi)| is ill-conditioned where the gradient vanishes
 # and theta does not).
+# "aniso": a planted mistake for one test -- the normal of Eq. (2) from two-point
+# axis differences, the non-isotropic choice Sec. III.A warns against -- so that
+# the run-level isotropy check can be shown to catch it.  Never a reference.
 _LIBS = {"plain": os.path.join(_HERE, "libdugks_oracle.so"),
-         "fma": os.path.join(_HERE, "libdugks_oracle_fma.so")}
-_FLAGS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]}
+         "fma": os.path.join(_HERE, "libdugks_oracle_fma.so"),
+         "aniso": os.path.join(_HERE, "libdugks_oracle_aniso.so")}
+_FLAGS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"],
+          "aniso": ["-ffp-contract=off", "-DORC_PLANT_ANISOTROPIC_NORMAL"]}
 _LIB = _LIBS["plain"]
 
 CENTRAL2, UPWIND3, CENTRAL4, UPWIND5 = 0, 1, 2, 3   # UPWIND5: T2S5 (oracle only)
@@ -36,9 +41,13 @@ VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = rang
 
 
 def build(force: bool = False, variant: str = "plain") -> str:
-    """Compile the oracle with gcc (OpenMP over rows) into its shared object."""
+    """Compile the oracle with gcc (OpenMP over rows) into its shared object
+    (again whenever the source is newer than it)."""
     out = _LIBS[variant]
-    if force or not os.path.exists(out):
+    stale = (not os.path.exists(out) or
+             os.path.getmtime(out) < max(os.path.getmtime(_SRC),
+                                         os.path.getmtime(os.path.join(_HERE, "dugks_oracle.h"))))
+    if force or stale:
         tmp = out + ".tmp"
         cmd = ["gcc", "-O2", *_FLAGS[variant], "-fopenmp", "-std=c11",
                "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-shared", "-fPIC",

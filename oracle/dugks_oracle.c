@@ -45,8 +45,18 @@ static const double WQ[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                              1.0 / 9.0,  1.0 / 36.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 9.0,  1.0 / 36.0};
 static const double RT = 1.0 / 3.0;
-/* Guard of n = g / |g| where the gradient vanishes (reading: continuous cap). */
-static const double NORMAL_EPS = 1e-12;
+/* Eq. (2) is singular where grad(phi) vanishes (at the extrema of the small
+ * over- and undershoots the schemes produce, where theta is not zero).
+ * Reading: |grad(phi)| in the denominator of n is regularised,
+ *   n = g / sqrt(|g|^2 + NORMAL_EPS^2),
+ * which is g/|g| to within (NORMAL_EPS/|g|)^2/2 wherever an interface is
+ * resolved, and a continuous function of g (slope <= 1/NORMAL_EPS) through
+ * g = 0, so that rounding moves the source term by rounding-sized amounts. */
+static const double NORMAL_EPS = 1e-4;
+
+static double normal_denominator(double gx, double gy) {
+  return sqrt(gx * gx + gy * gy + NORMAL_EPS * NORMAL_EPS);
+}
 
 /* Grids below this many cells run their loops on one thread: the fork / join
  * of a parallel region costs more than their work (and every cell's value is
@@ -180,6 +190,21 @@ static void hess_at(int nx, int ny, const double *a, int x, int y, double *hxx,
   *hxx = sxx / (RT * RT);
   *hxy = sxy / (RT * RT);
   *hyy = syy / (RT * RT);
+}
+
+/* Gradient of phi for the normal n of Eq. (2): the isotropic one above.  A
+ * test-only build (-DORC_PLANT_ANISOTROPIC_NORMAL) plants the mistake the
+ * paper warns against in Sec. III.A -- two-point differences along the axes,
+ * whose leading error is not isotropic -- so that a test can show that its
+ * run-level isotropy check fails for it; the oracle itself never defines it. */
+static void normal_grad_at(int nx, int ny, const double *a, int x, int y,
+                           double *gx, double *gy) {
+#ifdef ORC_PLANT_ANISOTROPIC_NORMAL
+  *gx = 0.5 * (a[IDX(nx, wrap(x + 1, nx), y)] - a[IDX(nx, wrap(x - 1, nx), y)]);
+  *gy = 0.5 * (a[IDX(nx, x, wrap(y + 1, ny))] - a[IDX(nx, x, wrap(y - 1, ny))]);
+#else
+  grad_at(nx, ny, a, x, y, gx, gy);
+#endif
 }
 
 void oracle_grad(int nx, int ny, const double *a, double *gx, double *gy) {
@@ -459,9 +484,8 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
       double gx, gy;
-      grad_at(nx, ny, phi, x, y, &gx, &gy);
-      double g = sqrt(gx * gx + gy * gy);
-      double d = g > NORMAL_EPS ? g : NORMAL_EPS;
+      normal_grad_at(nx, ny, phi, x, y, &gx, &gy);
+      double d = normal_denominator(gx, gy);
       nvx[c] = gx / d;
       nvy[c] = gy / d;
       theta[c] = theta_of(phi[c], p->width);
@@ -572,9 +596,8 @@ static void cell_terms(const oracle_params *p, const double *phi, double t,
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
       double gx, gy;
-      grad_at(nx, ny, phi, x, y, &gx, &gy);
-      double g = sqrt(gx * gx + gy * gy);
-      double d = g > NORMAL_EPS ? g : NORMAL_EPS;
+      normal_grad_at(nx, ny, phi, x, y, &gx, &gy);
+      double d = normal_denominator(gx, gy);
       double u, v, jx = 0.0, jy = 0.0, fe[9], sr[9];
       cell_velocity(p, x, y, t, &u, &v);
       if (with_j && !p->dtphiu_zero) {
@@ -712,9 +735,8 @@ int oracle_init(const oracle_params *p, const double *phi0, double *tf,
     for (int x = 0; x < nx; x++) {
       size_t c = IDX(nx, x, y);
       double gx, gy;
-      grad_at(nx, ny, phi0, x, y, &gx, &gy);
-      double g = sqrt(gx * gx + gy * gy);
-      double d = g > NORMAL_EPS ? g : NORMAL_EPS;
+      normal_grad_at(nx, ny, phi0, x, y, &gx, &gy);
+      double d = normal_denominator(gx, gy);
       double theta = theta_of(phi0[c], p->width);
       double u, v, fe[9], sr[9];
       cell_velocity(p, x, y, 0.0, &u, &v);

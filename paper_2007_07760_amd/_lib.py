@@ -61,7 +61,10 @@ def load() -> ctypes.CDLL:
     L.dugks_plan_destroy.restype = None
     L.dugks_state_bytes.argtypes = [vp]
     L.dugks_state_bytes.restype = ctypes.c_size_t
-    L.dugks_init.argtypes = [vp, vp, vp, vp]
+    L.dugks_init.argtypes = [vp, vp, vp, vp, vp]
+    L.dugks_history.argtypes = [vp, vp, i64, vp, vp]
+    L.dugks_state_status.argtypes = [vp, vp, vp, vp]
+    L.dugks_batch_status.argtypes = [vp, vp, vp]
     L.dugks_step.argtypes = [vp, vp, i64, i64, vp]
     L.dugks_phi.argtypes = [vp, vp, i64, vp, vp]
     L.dugks_mass.argtypes = [vp, vp, i64, vp, vp]
@@ -84,7 +87,7 @@ def load() -> ctypes.CDLL:
     L.dugks_batch_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     L.dugks_tune.argtypes = [P, vp, i64, i32, ctypes.POINTER(i32), vp]
     for name in ("dugks_plan_create", "dugks_init", "dugks_step", "dugks_phi",
-                 "dugks_distributions",
+                 "dugks_distributions", "dugks_history", "dugks_state_status", "dugks_batch_status",
                  "dugks_mass", "dugks_mass_correct", "dugks_mass0",
                  "dugks_batch_create", "dugks_batch_set", "dugks_batch_clear",
                  "dugks_batch_commit", "dugks_batch_step", "dugks_batch_steps",
@@ -148,8 +151,8 @@ def dugks_state_bytes(plan: int) -> int:
     return load().dugks_state_bytes(plan)
 
 
-def dugks_init(plan: int, state: int, phi0_dev: int, stream: int) -> None:
-    _check(load().dugks_init(plan, state, phi0_dev, stream), "dugks_init")
+def dugks_init(plan: int, state: int, phi0_dev: int, uv_dev, stream: int) -> None:
+    _check(load().dugks_init(plan, state, phi0_dev, uv_dev, stream), "dugks_init")
 
 
 def dugks_step(plan: int, state: int, step: int, nsteps: int, stream: int) -> None:
@@ -164,6 +167,18 @@ def dugks_distributions(plan: int, state: int, step: int, out_dev: int,
                         stream: int) -> None:
     _check(load().dugks_distributions(plan, state, step, out_dev, stream),
            "dugks_distributions")
+
+
+def dugks_history(plan: int, state: int, step: int, out_dev: int, stream: int) -> None:
+    _check(load().dugks_history(plan, state, step, out_dev, stream), "dugks_history")
+
+
+def dugks_state_status(plan: int, state: int, out: int, stream: int) -> None:
+    _check(load().dugks_state_status(plan, state, out, stream), "dugks_state_status")
+
+
+def dugks_batch_status(batch: int, out: int, stream: int) -> None:
+    _check(load().dugks_batch_status(batch, out, stream), "dugks_batch_status")
 
 
 def dugks_mass(plan: int, state: int, step: int, out_dev: int, stream: int) -> None:

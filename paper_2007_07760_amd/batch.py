@@ -52,6 +52,17 @@ class Batch:
     def step(self, nsteps: int, graph_steps: int = 16) -> None:
         C.dugks_batch_step(self.handle, int(nsteps), int(graph_steps), self.stream())
 
+    def status_async(self, out: torch.Tensor) -> None:
+        """Queue a copy of each slot's status (int32; OK or ENUMERIC) into `out`."""
+        C.dugks_batch_status(self.handle, out.data_ptr(), self.stream())
+
+    def status(self) -> np.ndarray:
+        """Status per slot, shape (capacity,); waits for the stream."""
+        out = torch.zeros(self.capacity, dtype=torch.int32, pin_memory=True)
+        self.status_async(out)
+        torch.cuda.current_stream().synchronize()
+        return out.numpy().copy()
+
     def steps_async(self, out: torch.Tensor) -> None:
         """Queue a copy of the (step, target) pairs into `out` (pinned int64)."""
         C.dugks_batch_steps(self.handle, out.data_ptr(), self.stream())

@@ -194,7 +194,6 @@ int validate(const dugks_params* p) {
   if ((p->vel_kind == DUGKS_VEL_SINGLE_VORTEX || p->vel_kind == DUGKS_VEL_DEFORMATION) &&
       !(p->vel_param[1] > 0.0))
     return DUGKS_EINVAL;
-  if (p->vel_kind == DUGKS_VEL_ARRAYS) return DUGKS_EUNSUPPORTED;
   return DUGKS_OK;
 }
 
@@ -244,13 +243,21 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s, boo
   StateHeader* hd = at<StateHeader>(state, 0);
   const int per = (a.nlogical + 7) / 8;
   dim3 grid(per * 8), block(LANES);
-#define DUGKS_LAUNCH(RR)                                                                       \
-  hipLaunchKernelGGL((step_kernel<T, RR, MFIX, STAGE>), grid, block, 0, s, a, n, q.src, q.dst, \
-                     dst2, aux, q.cf, q.tabx, q.taby, part, hd)
+  const bool varr = P->p.vel_kind == DUGKS_VEL_ARRAYS;
+  const T* uv = varr ? at<T>(state, L.off_vel) : nullptr;
+#define DUGKS_LAUNCH(RR, VA)                                                                   \
+  hipLaunchKernelGGL((step_kernel<T, RR, MFIX, STAGE, VA>), grid, block, 0, s, a, n, q.src,    \
+                     q.dst, dst2, aux, q.cf, q.tabx, q.taby, uv, part, hd)
   switch (P->p.recon) {
-    case DUGKS_CENTRAL2: DUGKS_LAUNCH(DUGKS_CENTRAL2); break;
-    case DUGKS_UPWIND3: DUGKS_LAUNCH(DUGKS_UPWIND3); break;
-    default: DUGKS_LAUNCH(DUGKS_CENTRAL4); break;
+    case DUGKS_CENTRAL2:
+      if (varr) DUGKS_LAUNCH(DUGKS_CENTRAL2, true); else DUGKS_LAUNCH(DUGKS_CENTRAL2, false);
+      break;
+    case DUGKS_UPWIND3:
+      if (varr) DUGKS_LAUNCH(DUGKS_UPWIND3, true); else DUGKS_LAUNCH(DUGKS_UPWIND3, false);
+      break;
+    default:
+      if (varr) DUGKS_LAUNCH(DUGKS_CENTRAL4, true); else DUGKS_LAUNCH(DUGKS_CENTRAL4, false);
+      break;
   }
 #undef DUGKS_LAUNCH
   if (MFIX && fix)
@@ -307,7 +314,8 @@ int stage_head(const dugks_plan* P) {
 }
 
 template <typename T>
-int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s) {
+int do_init(const dugks_plan* P, void* state, const double* phi0, const double* uv,
+            hipStream_t s) {
   const Layout& L = P->L;
   const int nx = P->p.nx, ny = P->p.ny;
   std::call_once(P->staged, [P] { P->head_rc = stage_head<T>(P); });
@@ -316,6 +324,14 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   if ((e = hipMemcpyAsync(state, P->head, L.off_buf[0], hipMemcpyHostToDevice, s)))
     return hip_status(e);
   InitArgs<T> a;
+  a.uv = nullptr;
+  if (P->p.vel_kind == DUGKS_VEL_ARRAYS) {
+    const int64_t n2 = 2 * (int64_t)nx * ny;
+    T* dst = at<T>(state, L.off_vel);
+    hipLaunchKernelGGL((velocity_store_kernel<T>), dim3((unsigned)((n2 + 255) / 256)), dim3(256),
+                       0, s, uv, dst, n2);
+    a.uv = dst;
+  }
   a.phi0 = phi0;
   a.buf = at<T>(state, L.off_buf[0]);
   a.tabx = at<T>(state, L.off_tabx);
@@ -332,7 +348,7 @@ int do_init(const dugks_plan* P, void* state, const double* phi0, hipStream_t s)
   hipLaunchKernelGGL((mass_partial_kernel<double, false>), dim3(MASS_BLOCKS), dim3(MASS_THREADS),
                      0, s, phi0, L.tl, nullptr, part);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass0,
-                     &hd->mass_now);
+                     &hd->mass_now, hd);
   return hip_status(hipGetLastError());
 }
 
@@ -357,13 +373,22 @@ int do_export(const dugks_plan* P, const void* state, int64_t n, void* out, hipS
 }
 
 template <typename T>
+int do_history(const dugks_plan* P, const void* state, int64_t n, void* out, hipStream_t s) {
+  const Layout& L = P->L;
+  dim3 grid((P->p.nx + 255) / 256, P->p.ny), block(256);
+  hipLaunchKernelGGL((history_kernel<T>), grid, block, 0, s, at<T>(state, L.off_buf[n & 1]),
+                     L.tl, static_cast<T*>(out));
+  return hip_status(hipGetLastError());
+}
+
+template <typename T>
 int do_mass(const dugks_plan* P, void* state, int64_t n, double* out, hipStream_t s) {
   const Layout& L = P->L;
   double* part = at<double>(state, L.off_scratch);
   StateHeader* hd = at<StateHeader>(state, 0);
   hipLaunchKernelGGL((mass_partial_kernel<T, true>), dim3(MASS_BLOCKS), dim3(MASS_THREADS), 0, s,
                      at<T>(state, L.off_buf[n & 1]), L.tl, hd, part);
-  hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass_now, out);
+  hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(64), 0, s, part, &hd->mass_now, out, hd);
   return hip_status(hipGetLastError());
 }
 
@@ -396,7 +421,7 @@ int dugks_plan_create(const dugks_params* p, dugks_plan** out) {
   dugks_plan* P = new (std::nothrow) dugks_plan();
   if (!P) return DUGKS_ENOMEM;
   P->p = *p;
-  P->L = make_layout(p->nx, p->ny, p->precision, p->scheme);
+  P->L = make_layout(p->nx, p->ny, p->precision, p->scheme, p->vel_kind);
   P->dt = p->cfl;                 // Eq. (39), dx = sqrt(3RT) = 1
   P->h = 0.5 * P->dt;
   P->tau = p->mobility / RT;      // M_phi = tau RT
@@ -478,11 +503,13 @@ void dugks_plan_destroy(dugks_plan* plan) {
 
 size_t dugks_state_bytes(const dugks_plan* plan) { return plan ? plan->L.total : 0; }
 
-int dugks_init(const dugks_plan* plan, void* state, const double* phi0_dev, void* stream) {
+int dugks_init(const dugks_plan* plan, void* state, const double* phi0_dev,
+               const double* uv_dev, void* stream) {
   if (!plan || !state || !phi0_dev || !aligned(state)) return DUGKS_EINVAL;
+  if (plan->p.vel_kind == DUGKS_VEL_ARRAYS && !uv_dev) return DUGKS_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return plan->p.precision == DUGKS_F64 ? do_init<double>(plan, state, phi0_dev, s)
-                                        : do_init<float>(plan, state, phi0_dev, s);
+  return plan->p.precision == DUGKS_F64 ? do_init<double>(plan, state, phi0_dev, uv_dev, s)
+                                        : do_init<float>(plan, state, phi0_dev, uv_dev, s);
 }
 
 int dugks_step(const dugks_plan* plan, void* state, int64_t step, int64_t nsteps,
@@ -571,6 +598,22 @@ int dugks_distributions(const dugks_plan* plan, const void* state, int64_t step,
   hipStream_t s = static_cast<hipStream_t>(stream);
   return plan->p.precision == DUGKS_F64 ? do_export<double>(plan, state, step, out_dev, s)
                                         : do_export<float>(plan, state, step, out_dev, s);
+}
+
+int dugks_history(const dugks_plan* plan, const void* state, int64_t step, void* out_dev,
+                  void* stream) {
+  if (!plan || !state || !out_dev || !aligned(state) || step < 0) return DUGKS_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return plan->p.precision == DUGKS_F64 ? do_history<double>(plan, state, step, out_dev, s)
+                                        : do_history<float>(plan, state, step, out_dev, s);
+}
+
+int dugks_state_status(const dugks_plan* plan, const void* state, int32_t* status_out,
+                 void* stream) {
+  if (!plan || !state || !status_out || !aligned(state)) return DUGKS_EINVAL;
+  const StateHeader* hd = at<StateHeader>(state, 0);
+  return hip_status(hipMemcpyAsync(status_out, &hd->status, sizeof(int32_t), hipMemcpyDefault,
+                                   static_cast<hipStream_t>(stream)));
 }
 
 int dugks_mass(const dugks_plan* plan, void* state, int64_t step, double* mass_out_dev,

@@ -11,6 +11,7 @@
 #include "dugks_common.h"
 #include "dugks_kernels.h"
 #include "dugks_plan.h"
+#include "dugks_batch_impl.h"
 
 using namespace dugks;
 
@@ -31,6 +32,84 @@ struct Slot {
 
 }  // namespace
 
+namespace dugks {
+
+template <typename T, int R, bool MFIX>
+static int launch_batch_step(const BatchDev& D, int scheme, hipStream_t s, bool finish) {
+  const GridDesc<T>* desc = static_cast<const GridDesc<T>*>(D.desc);
+  if (scheme == DUGKS_T3S3) {   // the two stages over every tile, in turn
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_A>), dim3(D.grid_blocks),
+                       dim3(LANES), 0, s, desc, D.steps, D.ctl, D.head);
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_B>), dim3(D.grid_blocks),
+                       dim3(LANES), 0, s, desc, D.steps, D.ctl, D.head);
+  } else {
+    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(D.grid_blocks), dim3(LANES), 0, s,
+                       desc, D.steps, D.ctl, D.head);
+  }
+  if (finish)
+    hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(D.nslots), dim3(FIX_THREADS), 0, s,
+                       desc, D.steps, D.head, D.status);
+  return hip_status(hipGetLastError());
+}
+
+int launch_batch(const BatchDev& D, int precision, int recon, bool mfix, int scheme,
+                 hipStream_t s, bool finish) {
+#define DUGKS_BATCH(TT, RR)                                                    \
+  return mfix ? launch_batch_step<TT, RR, true>(D, scheme, s, finish)          \
+              : launch_batch_step<TT, RR, false>(D, scheme, s, finish)
+#define DUGKS_BATCH_R(TT)                                        \
+  switch (recon) {                                               \
+    case DUGKS_CENTRAL2: DUGKS_BATCH(TT, DUGKS_CENTRAL2);        \
+    case DUGKS_UPWIND3: DUGKS_BATCH(TT, DUGKS_UPWIND3);          \
+    default: DUGKS_BATCH(TT, DUGKS_CENTRAL4);                    \
+  }
+  if (precision == DUGKS_F64) {
+    DUGKS_BATCH_R(double)
+  } else {
+    DUGKS_BATCH_R(float)
+  }
+#undef DUGKS_BATCH_R
+#undef DUGKS_BATCH
+}
+
+template <typename T, int R, bool MFIX>
+static int occupancy(int* per_cu, int scheme) {
+  if (scheme == DUGKS_T3S3) {   // the smaller of the two stages' residencies
+    int a = 0, b = 0;
+    int rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &a, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_A>), LANES, 0));
+    if (!rc)
+      rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_B>), LANES,
+          0));
+    *per_cu = std::min(a, b);
+    return rc;
+  }
+  return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX>), LANES, 0));
+}
+
+int batch_occupancy(int precision, int recon, bool mfix, int scheme, int* per_cu) {
+#define DUGKS_OCC(TT, RR)                                   \
+  return mfix ? occupancy<TT, RR, true>(per_cu, scheme)     \
+              : occupancy<TT, RR, false>(per_cu, scheme)
+#define DUGKS_OCC_R(TT)                                 \
+  switch (recon) {                                      \
+    case DUGKS_CENTRAL2: DUGKS_OCC(TT, DUGKS_CENTRAL2);  \
+    case DUGKS_UPWIND3: DUGKS_OCC(TT, DUGKS_UPWIND3);    \
+    default: DUGKS_OCC(TT, DUGKS_CENTRAL4);              \
+  }
+  if (precision == DUGKS_F64) {
+    DUGKS_OCC_R(double)
+  } else {
+    DUGKS_OCC_R(float)
+  }
+#undef DUGKS_OCC_R
+#undef DUGKS_OCC
+}
+
+}  // namespace dugks
+
 struct dugks_batch {
   int cap = 0, precision = 0, recon = 0;
   int scheme = DUGKS_T2;              // every attached plan's time scheme
@@ -40,6 +119,7 @@ struct dugks_batch {
   // device memory owned by the batch
   void* d_desc = nullptr;             // GridDesc<T>[cap]
   SlotStep* d_steps = nullptr;        // [cap]
+  int32_t* d_status = nullptr;        // [cap] status of each slot's state
   BatchCtl* d_ctl = nullptr;
   unsigned* d_head = nullptr;
   BatchItem* d_items = nullptr;
@@ -66,37 +146,7 @@ namespace {
 
 template <typename T>
 GridDesc<T> make_desc(const Slot& s, int rows) {
-  GridDesc<T> d;
-  memset(&d, 0, sizeof(d));
-  if (!s.plan) return d;
-  const dugks_plan* P = s.plan;
-  const Layout& L = P->L;
-  const bool t3 = P->p.scheme == DUGKS_T3S3;
-  d.a = step_args<T>(P, t3 ? STAGE_A : STAGE_T2);
-  d.b = step_args<T>(P, t3 ? STAGE_B : STAGE_T2);
-  const int seg = std::min(rows, P->p.ny);
-  for (StepArgs<T>* a : {&d.a, &d.b}) {
-    a->seg_rows = seg;
-    a->nsegs = (P->p.ny + seg - 1) / seg;
-    a->nlogical = a->nstrips * a->nsegs;
-  }
-  if (t3) {
-    d.mid = at<T>(s.state, L.off_mid);
-    d.q = at<T>(s.state, L.off_q);
-    d.cf2 = at<T>(s.state, L.off_coef2);
-  }
-  d.buf[0] = at<T>(s.state, L.off_buf[0]);
-  d.buf[1] = at<T>(s.state, L.off_buf[1]);
-  d.cf = at<T>(s.state, L.off_coef);
-  d.tabx = at<T>(s.state, L.off_tabx);
-  d.taby = at<T>(s.state, L.off_taby);
-  d.hdr = at<StateHeader>(s.state, 0);
-  d.part = at<double>(s.state, L.off_groups);
-  d.ncells = (double)P->p.nx * (double)P->p.ny;
-  d.strip_part = at<double>(s.state, L.off_strips);
-  d.groups_per_strip = L.ngroups;
-  d.nstrips = L.tl.nstrips;
-  return d;
+  return make_grid_desc<T>(s.plan, s.state, rows);
 }
 
 // Work list for tile height `rows`: every tile of every attached slot, the
@@ -145,7 +195,8 @@ int upload(dugks_batch* B, hipStream_t s) {
   if (rc) return rc;
   const size_t off_desc = 256;
   const size_t off_steps = align_up(off_desc + B->cap * sizeof(GridDesc<T>), 256);
-  const size_t off_items = align_up(off_steps + B->cap * sizeof(SlotStep), 256);
+  const size_t off_status = align_up(off_steps + B->cap * sizeof(SlotStep), 256);
+  const size_t off_items = align_up(off_status + B->cap * sizeof(int32_t), 256);
   const size_t need = off_items + B->items.size() * sizeof(BatchItem);
   const int j = B->stage_next;
   B->stage_next = (j + 1) % NSTAGE;
@@ -175,12 +226,16 @@ int upload(dugks_batch* B, hipStream_t s) {
     B->desc_dirty = false;
   }
   SlotStep* st = reinterpret_cast<SlotStep*>(h + off_steps);
+  int32_t* ss = reinterpret_cast<int32_t*>(h + off_status);
   for (int k = 0; k < B->cap; k++) {
     Slot& sl = B->slots[k];
     if (!sl.step_dirty) continue;
     st[k].n = sl.step;
     st[k].target = sl.target;
-    if ((e = hipMemcpyAsync(B->d_steps + k, st + k, sizeof(SlotStep), hipMemcpyHostToDevice, s)))
+    ss[k] = DUGKS_OK;   // a newly attached (or cleared) slot has no status yet
+    if ((e = hipMemcpyAsync(B->d_steps + k, st + k, sizeof(SlotStep), hipMemcpyHostToDevice,
+                            s)) ||
+        (e = hipMemcpyAsync(B->d_status + k, ss + k, sizeof(int32_t), hipMemcpyHostToDevice, s)))
       return hip_status(e);
     sl.step_dirty = false;
   }
@@ -194,80 +249,13 @@ int upload(dugks_batch* B, hipStream_t s) {
   return hip_status(hipEventRecord(B->stage_ev[j], s));
 }
 
-template <typename T, int R, bool MFIX>
-int launch_batch_step(dugks_batch* B, hipStream_t s, bool finish) {
-  const GridDesc<T>* desc = static_cast<const GridDesc<T>*>(B->d_desc);
-  if (B->scheme == DUGKS_T3S3) {   // the two stages over every tile, in turn
-    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_A>), dim3(B->grid_blocks),
-                       dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
-    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX, STAGE_B>), dim3(B->grid_blocks),
-                       dim3(LANES), 0, s, desc, B->d_steps, B->d_ctl, B->d_head);
-  } else {
-    hipLaunchKernelGGL((batch_step_kernel<T, R, MFIX>), dim3(B->grid_blocks), dim3(LANES), 0, s,
-                       desc, B->d_steps, B->d_ctl, B->d_head);
-  }
-  if (finish)
-    hipLaunchKernelGGL((batch_finish_kernel<T, MFIX>), dim3(B->cap), dim3(FIX_THREADS), 0, s,
-                       static_cast<const GridDesc<T>*>(B->d_desc), B->d_steps, B->d_head);
-  return hip_status(hipGetLastError());
-}
-
 // finish = false: the step kernel alone, which writes only the next-step
 // buffers and mass partials of each active slot (used to time tilings; the
 // state is unchanged, since the finish kernel never runs)
 int batch_launch(dugks_batch* B, hipStream_t s, bool finish) {
-#define DUGKS_BATCH(TT, RR)                                                    \
-  return B->mfix ? launch_batch_step<TT, RR, true>(B, s, finish)               \
-                 : launch_batch_step<TT, RR, false>(B, s, finish)
-#define DUGKS_BATCH_R(TT)                                        \
-  switch (B->recon) {                                            \
-    case DUGKS_CENTRAL2: DUGKS_BATCH(TT, DUGKS_CENTRAL2);        \
-    case DUGKS_UPWIND3: DUGKS_BATCH(TT, DUGKS_UPWIND3);          \
-    default: DUGKS_BATCH(TT, DUGKS_CENTRAL4);                    \
-  }
-  if (B->precision == DUGKS_F64) {
-    DUGKS_BATCH_R(double)
-  } else {
-    DUGKS_BATCH_R(float)
-  }
-#undef DUGKS_BATCH_R
-#undef DUGKS_BATCH
-}
-
-template <typename T, int R, bool MFIX>
-int occupancy(int* per_cu, int scheme) {
-  if (scheme == DUGKS_T3S3) {   // the smaller of the two stages' residencies
-    int a = 0, b = 0;
-    int rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &a, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_A>), LANES, 0));
-    if (!rc)
-      rc = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &b, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX, STAGE_B>), LANES,
-          0));
-    *per_cu = std::min(a, b);
-    return rc;
-  }
-  return hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      per_cu, reinterpret_cast<const void*>(&batch_step_kernel<T, R, MFIX>), LANES, 0));
-}
-
-int batch_occupancy(const dugks_batch* B, int* per_cu) {
-#define DUGKS_OCC(TT, RR)                                   \
-  return B->mfix ? occupancy<TT, RR, true>(per_cu, B->scheme) \
-                 : occupancy<TT, RR, false>(per_cu, B->scheme)
-#define DUGKS_OCC_R(TT)                                 \
-  switch (B->recon) {                                   \
-    case DUGKS_CENTRAL2: DUGKS_OCC(TT, DUGKS_CENTRAL2);  \
-    case DUGKS_UPWIND3: DUGKS_OCC(TT, DUGKS_UPWIND3);    \
-    default: DUGKS_OCC(TT, DUGKS_CENTRAL4);              \
-  }
-  if (B->precision == DUGKS_F64) {
-    DUGKS_OCC_R(double)
-  } else {
-    DUGKS_OCC_R(float)
-  }
-#undef DUGKS_OCC_R
-#undef DUGKS_OCC
+  const BatchDev D{B->d_desc, B->d_steps, B->d_status, B->d_ctl, B->d_head, B->cap,
+                   B->grid_blocks};
+  return launch_batch(D, B->precision, B->recon, B->mfix, B->scheme, s, finish);
 }
 
 int commit(dugks_batch* B, hipStream_t s) {
@@ -289,6 +277,7 @@ void release(dugks_batch* B) {
   if (B->d_items) (void)hipFree(B->d_items);
   if (B->d_desc) (void)hipFree(B->d_desc);
   if (B->d_steps) (void)hipFree(B->d_steps);
+  if (B->d_status) (void)hipFree(B->d_status);
   if (B->d_ctl) (void)hipFree(B->d_ctl);
   if (B->d_head) (void)hipFree(B->d_head);
 }
@@ -344,14 +333,19 @@ int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint3
   if (hipGetDevice(&B->device) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) !=
           hipSuccess ||
-      (rc = batch_occupancy(B, &per_cu)) != DUGKS_OK || per_cu < 1 || ncu < 1 ||
+      (rc = batch_occupancy(B->precision, B->recon, B->mfix, B->scheme, &per_cu)) !=
+          DUGKS_OK ||
+      per_cu < 1 || ncu < 1 ||
       hipMalloc(&B->d_desc, capacity * B->desc_bytes) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&B->d_steps), capacity * sizeof(SlotStep)) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&B->d_status), capacity * sizeof(int32_t)) !=
           hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&B->d_ctl), sizeof(BatchCtl)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&B->d_head), 256) != hipSuccess ||
       hipMemset(B->d_desc, 0, capacity * B->desc_bytes) != hipSuccess ||
       hipMemset(B->d_steps, 0, capacity * sizeof(SlotStep)) != hipSuccess ||
+      hipMemset(B->d_status, 0, capacity * sizeof(int32_t)) != hipSuccess ||
       hipMemset(B->d_ctl, 0, sizeof(BatchCtl)) != hipSuccess ||
       hipMemset(B->d_head, 0, 256) != hipSuccess ||
       hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -391,6 +385,7 @@ int dugks_batch_set(dugks_batch* batch, int32_t slot, const dugks_plan* plan, vo
       ((plan->p.flags & DUGKS_FLAG_MASS_FIX) != 0) != batch->mfix ||
       plan->p.scheme != batch->scheme)
     return DUGKS_EINVAL;
+  if (plan->p.vel_kind == DUGKS_VEL_ARRAYS) return DUGKS_EUNSUPPORTED;
   Slot& s = batch->slots[slot];
   s.plan = plan;
   s.state = state;
@@ -435,6 +430,12 @@ int dugks_batch_step(dugks_batch* batch, int64_t nsteps, int32_t graph_steps, vo
 int dugks_batch_steps(const dugks_batch* batch, int64_t* out, void* stream) {
   if (!batch || !out) return DUGKS_EINVAL;
   return hip_status(hipMemcpyAsync(out, batch->d_steps, batch->cap * sizeof(SlotStep),
+                                   hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+}
+
+int dugks_batch_status(const dugks_batch* batch, int32_t* out, void* stream) {
+  if (!batch || !out) return DUGKS_EINVAL;
+  return hip_status(hipMemcpyAsync(out, batch->d_status, batch->cap * sizeof(int32_t),
                                    hipMemcpyDefault, static_cast<hipStream_t>(stream)));
 }
 

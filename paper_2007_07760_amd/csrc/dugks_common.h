@@ -134,7 +134,7 @@ struct StateHeader {
   int32_t nx, ny, precision, recon;
   double fit_max;      // fused correction: cells with stored f~_0 below it take it
   int32_t fix_count;   // fused correction: strips reduced so far in this step
-  int32_t pad32;
+  int32_t status;      // DUGKS_OK, or DUGKS_ENUMERIC once a non-finite total was seen
   int64_t pad[24];
 };
 static_assert(sizeof(StateHeader) == 256, "header size");
@@ -150,17 +150,25 @@ constexpr int MASS_GROUP = 8;
 constexpr double MASS_FIT_MAX = 1e-3;
 constexpr int FIX_THREADS = 1024;   // threads of the block that reduces the groups
 
+// The unit normal of Eq. (2) is read as n = g / sqrt(|g|^2 + NORMAL_EPS^2), g
+// the isotropic gradient of phi: n = g/|g| to within (NORMAL_EPS/|g|)^2/2 on
+// every interface, and a continuous function of g with a slope bounded by
+// 1/NORMAL_EPS where the gradient vanishes (at the extrema of the scheme's
+// small over- and undershoots), so that rounding at such a point moves the
+// source term by rounding-sized amounts rather than by flipping n.
+constexpr double NORMAL_EPS = 1e-4;
+
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)
   Tiling tl;
-  size_t off_coef, off_coef2, off_tabx, off_taby, off_buf[2], off_mid, off_q;
+  size_t off_coef, off_coef2, off_tabx, off_taby, off_vel, off_buf[2], off_mid, off_q;
   size_t off_scratch, off_groups, off_strips, total;
   int ngroups;         // row groups per strip
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline Layout make_layout(int nx, int ny, int precision, int scheme) {
+inline Layout make_layout(int nx, int ny, int precision, int scheme, int vel_kind) {
   Layout L;
   L.esize = precision == DUGKS_F64 ? 8 : 4;
   const int64_t line = 128 / (int64_t)L.esize;
@@ -178,6 +186,13 @@ inline Layout make_layout(int nx, int ny, int precision, int scheme) {
   off = align_up(off + 2 * (2 * (size_t)nx + 2) * L.esize, 256);
   L.off_taby = off;
   off = align_up(off + 2 * (2 * (size_t)ny + 2) * L.esize, 256);
+  // caller-supplied cell velocities (DUGKS_VEL_ARRAYS): u plane, v plane,
+  // [ny][nx] dense in the plan's precision
+  L.off_vel = 0;
+  if (vel_kind == DUGKS_VEL_ARRAYS) {
+    L.off_vel = off;
+    off = align_up(off + 2 * (size_t)nx * ny * L.esize, 256);
+  }
   for (int b = 0; b < 2; b++) {
     L.off_buf[b] = off;
     off = align_up(off + buf_elems * L.esize, 256);

@@ -177,16 +177,19 @@ __device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
   x[4] = P2 + dmp; x[8] = P2 - dmp;
 }
 
-// num / max(|g|, 1e-12), the square root and the quotient rounded exactly (a
-// hardware reciprocal square root in FP32 was ~1 % faster, but moved the
-// FP32 field of the 64^2 translation by 5x more in L-inf)
+// num / sqrt(|g|^2 + NORMAL_EPS^2) (the regularised |g| of the normal), the
+// square root and the quotient rounded exactly (a hardware reciprocal square
+// root in FP32 was ~1 % faster, but moved the FP32 field of the 64^2
+// translation by 5x more in L-inf)
 template <typename T>
 __device__ __forceinline__ T over_norm(T num, T gx, T gy) {
-  const T gm = sqrt(fma(gx, gx, gy * gy));
-  return num / (gm > T(1e-12) ? gm : T(1e-12));
+  const T e2 = T(NORMAL_EPS * NORMAL_EPS);
+  return num / sqrt(fma(gx, gx, fma(gy, gy, e2)));
 }
 
-template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
+// VARR: the velocity comes from caller-supplied cell arrays (steady; a face
+// takes the mean of its two cells) instead of the separable tables.
+template <typename T, int R, bool MFIX, int STAGE = STAGE_T2, bool VARR = false>
 struct Marcher {
   static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
   // the fused mass correction: the stored state's loads take the pending
@@ -200,6 +203,7 @@ struct Marcher {
   cptr<T> cf;
   const T* __restrict__ tabx;
   cptr<T> taby;
+  const T* __restrict__ uv;   // VARR: u plane then v plane, [ny][nx]
   T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
   int lane, col;
   int ocol;                 // owned lanes: column within the strip
@@ -231,6 +235,12 @@ struct Marcher {
   double* part_row;
 
   __device__ __forceinline__ T cw(int i) const { return i == 0 ? cw0 : ((i & 1) ? cw1 : cw2); }
+
+  // VARR: component c (0: u, 1: v) at the lane's cell of (wrapped) row rr;
+  // rows are read again at the faces two rows later, from the caches
+  __device__ __forceinline__ T uv_at(int c, int rr) const {
+    return uv[((int64_t)c * a.ny + rr) * a.nx + col];
+  }
 
   __device__ __forceinline__ int slotB(int row) const { return (row - base) % RB; }
 
@@ -274,9 +284,14 @@ struct Marcher {
     const T pC = ph2;
     const T th = over_norm(a.kth * pC * (T(1) - pC), gx, gy);   // theta / |grad phi|
     const int rr = wrapi(r, a.ny);
-    const T UYr = taby[2 * rr + 1];
-    const T VYr = taby[(2 * a.ny + 2) + 2 * rr + 1];
-    const T Uc = UXc * UYr, Vc = VXc * VYr;        // spatial part of u
+    T Uc, Vc;                                      // spatial part of u
+    if (VARR) {
+      Uc = uv_at(0, rr);
+      Vc = uv_at(1, rr);
+    } else {
+      Uc = UXc * taby[2 * rr + 1];
+      Vc = VXc * taby[(2 * a.ny + 2) + 2 * rr + 1];
+    }
     const T dj = fma(gN, pC, -(gP * d.hp)) * jscale;   // d(phi g)/dt
     const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
     const T sy = fma(th, gy, T(3) * (Vc * dj));
@@ -357,9 +372,19 @@ struct Marcher {
     }
     const cptr<T> UY = taby;
     const cptr<T> VY = taby + (2 * a.ny + 2);
-    // north face (x + 1/2, y + 1): S_b = mean of the two cells
-    const T ubN = gH * (UXc * UY[2 * kk + 2]);
-    const T vbN = gH * (VXc * VY[2 * kk + 2]);
+    // north face (x + 1/2, y + 1): S_b = mean of the two cells; a velocity
+    // array gives the mean of the two cells' velocities (steady)
+    T ubN, vbN, uk = T(0), vk = T(0);
+    if (VARR) {
+      const int k1 = wrapi(k + 1, a.ny);
+      uk = uv_at(0, kk);
+      vk = uv_at(1, kk);
+      ubN = T(0.5) * (uk + uv_at(0, k1));
+      vbN = T(0.5) * (vk + uv_at(1, k1));
+    } else {
+      ubN = gH * (UXc * UY[2 * kk + 2]);
+      vbN = gH * (VXc * VY[2 * kk + 2]);
+    }
     // phN = dt*alpha*phi_b; P = beta phi_b, Q = 3 P u_b + gamma s_b, all
     // carried pre-multiplied by dt so that dt f_b,i = pn_i + w_i (P + e_i.Q)
     const T PN = a.pscale * phN;
@@ -380,8 +405,8 @@ struct Marcher {
       out[8] += (a2 + ax2) - ay2;
     }
     // east face (x + 1, y + 1/2): S_b = mean of own and east cell
-    const T ubE = gH * (UXe * UY[2 * kk + 1]);
-    const T vbE = gH * (VXe * VY[2 * kk + 1]);
+    const T ubE = VARR ? T(0.5) * (uk + from_right(uk)) : gH * (UXe * UY[2 * kk + 1]);
+    const T vbE = VARR ? T(0.5) * (vk + from_right(vk)) : gH * (VXe * VY[2 * kk + 1]);
     const T PE = a.pscale * phE;
     const T QEx = fma(T(3) * PE, ubE, a.gdt * (sx0 + from_right(sx0)));
     const T QEy = fma(T(3) * PE, vbE, a.gdt * (sy0 + from_right(sy0)));
@@ -526,18 +551,19 @@ struct Marcher {
 // One tile: the strip `strip` of the grid, rows of segment `seg`, step n.
 // pend = per-cell mass correction delta still to apply to the stored f~ of the
 // cells whose stored f~_0 is below fitmax (MFIX).
-template <typename T, int R, bool MFIX, int STAGE = STAGE_T2>
+template <typename T, int R, bool MFIX, int STAGE = STAGE_T2, bool VARR = false>
 __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
                                            const T* __restrict__ src, T* __restrict__ dst,
                                            T* __restrict__ dst2, const T* __restrict__ aux,
                                            const T* __restrict__ cf,
                                            const T* __restrict__ tabx,
                                            const T* __restrict__ taby,
+                                           const T* __restrict__ uv,
                                            double* __restrict__ part, double pend,
                                            double fitmax, int strip,
                                            int seg, T (*s_bfp)[9][LROW]) {
-  Marcher<T, R, MFIX, STAGE> m{a, src, as_const(cf), tabx, as_const(taby),
-                               s_bfp};
+  Marcher<T, R, MFIX, STAGE, VARR> m{a, src, as_const(cf), tabx, as_const(taby), uv,
+                                     s_bfp};
   const int lane = threadIdx.x;
   const int x0 = strip * OWN;
   m.lane = lane;
@@ -562,11 +588,13 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   m.y0 = seg * a.seg_rows;
   m.y1 = min(m.y0 + a.seg_rows, a.ny);
   m.base = m.y0 - 3;
-  const int ce = m.col + 1;  // east face of the column (x + 1), unwrapped
-  m.UXc = tabx[2 * m.col + 1];
-  m.VXc = tabx[(2 * a.nx + 2) + 2 * m.col + 1];
-  m.UXe = tabx[2 * ce];
-  m.VXe = tabx[(2 * a.nx + 2) + 2 * ce];
+  if (!VARR) {
+    const int ce = m.col + 1;  // east face of the column (x + 1), unwrapped
+    m.UXc = tabx[2 * m.col + 1];
+    m.VXc = tabx[(2 * a.nx + 2) + 2 * m.col + 1];
+    m.UXe = tabx[2 * ce];
+    m.VXe = tabx[(2 * a.nx + 2) + 2 * ce];
+  }
   // time factors of the velocity at the stage's base time and at the time of
   // the earlier phi (cells), and at base + its half step (faces)
   const double tn = (double)n * a.dtd;
@@ -592,13 +620,14 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   m.run();
 }
 
-template <typename T, int R, bool MFIX, int STAGE>
+template <typename T, int R, bool MFIX, int STAGE, bool VARR>
 __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void
 step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__ dst,
             T* __restrict__ dst2, const T* __restrict__ aux, const T* __restrict__ cf,
-            const T* __restrict__ tabx, const T* __restrict__ taby, double* __restrict__ part,
+            const T* __restrict__ tabx, const T* __restrict__ taby,
+            const T* __restrict__ uv, double* __restrict__ part,
             const StateHeader* __restrict__ hdr) {
-  constexpr int RB = Marcher<T, R, MFIX, STAGE>::RB;
+  constexpr int RB = Marcher<T, R, MFIX, STAGE, VARR>::RB;
   __shared__ T s_bfp[RB][9][LROW];
 
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
@@ -614,8 +643,8 @@ step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__
   __syncthreads();
   const double pend = MFIX ? hdr->pending : 0.0;
   const double fitmax = MFIX ? hdr->fit_max : 0.0;
-  march_tile<T, R, MFIX, STAGE>(a, n, src, dst, dst2, aux, cf, tabx, taby, part, pend, fitmax,
-                                strip, seg, s_bfp);
+  march_tile<T, R, MFIX, STAGE, VARR>(a, n, src, dst, dst2, aux, cf, tabx, taby, uv, part,
+                                      pend, fitmax, strip, seg, s_bfp);
 }
 
 // Neumaier pair (sum, compensation)
@@ -635,12 +664,19 @@ __device__ __forceinline__ void neu_add(double& s, double& c, double v) {
 // with phi near 0), delta = (M0 - M^{n+1}) / count; where fewer than 1 % of
 // the cells qualify, to every cell, delta = (M0 - M^{n+1}) / N.  What rounding
 // still loses is in the next step's total and corrected then.
+// A non-finite total marks the state as blown up (sticky status ENUMERIC) and
+// sets no correction.
 __device__ __forceinline__ void mass_fix_set(StateHeader* __restrict__ hdr, double m_new,
                                              double nfit, double ncells) {
   const bool to_fit = nfit >= 0.01 * ncells && nfit >= 1.0;
   hdr->fit_max = to_fit ? MASS_FIT_MAX : INFINITY;
   hdr->mass_now = m_new;
-  hdr->pending = (hdr->mass0 - m_new) / (to_fit ? nfit : ncells);
+  if (isfinite(m_new)) {
+    hdr->pending = (hdr->mass0 - m_new) / (to_fit ? nfit : ncells);
+  } else {
+    hdr->pending = 0.0;
+    hdr->status = DUGKS_ENUMERIC;
+  }
 }
 
 // Fixed-order (Neumaier) sum of n pairs (v[2j], v[2j+1]) by one wavefront:
@@ -806,13 +842,15 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
     const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
     if (STAGE == STAGE_T2)
       march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf,
-                                    d->tabx, d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+                                    d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
+                                    s_bfp);
     else if (STAGE == STAGE_A)   // f^^n -> f~(t'), Q
       march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->mid, d->q, nullptr, d->cf, d->tabx,
-                                    d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+                                    d->taby, nullptr, d->part, pend, fitmax, strip, seg, s_bfp);
     else                         // f~(t'), Q -> f^^{n+1}
       march_tile<T, R, MFIX, STAGE>(a, n, d->mid, d->buf[b ^ 1], nullptr, d->q, d->cf2,
-                                    d->tabx, d->taby, d->part, pend, fitmax, strip, seg, s_bfp);
+                                    d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
+                                    s_bfp);
     // the next item's ring starts from its own rows; order this tile's LDS
     // reads before them
     wave_sync();
@@ -821,20 +859,28 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
 
 // After each batch step: per active slot, the fused mass correction (MFIX)
 // and n += 1; block 0 rewinds the work queue for the next step.
+// A slot whose state reports a non-finite total (status ENUMERIC: from its
+// first state, or from this step's fused correction) stops here: its target
+// becomes the step it has reached, and the status is kept for the caller.
 template <typename T, bool MFIX>
 __global__ __launch_bounds__(FIX_THREADS) void batch_finish_kernel(
     const GridDesc<T>* __restrict__ desc, SlotStep* __restrict__ steps,
-    unsigned* __restrict__ head) {
+    unsigned* __restrict__ head, int32_t* __restrict__ status) {
   const int slot = blockIdx.x;
   if (slot == 0 && threadIdx.x < 2) head[threadIdx.x] = 0u;   // both queue heads
   const int64_t n = steps[slot].n;
   if (n >= steps[slot].target) return;
+  const GridDesc<T>& d = desc[slot];
   if (MFIX) {
-    const GridDesc<T>& d = desc[slot];
     mass_fix_block(d.part, d.groups_per_strip, d.nstrips, d.strip_part, d.hdr, d.ncells);
     __syncthreads();
   }
-  if (threadIdx.x == 0) steps[slot].n = n + 1;
+  if (threadIdx.x == 0) {
+    const int32_t st = d.hdr->status;
+    status[slot] = st;
+    steps[slot].n = n + 1;
+    if (st != DUGKS_OK) steps[slot].target = n + 1;
+  }
 }
 
 // ------------------------------------------------------------------ init
@@ -844,9 +890,19 @@ struct InitArgs {
   T* __restrict__ buf;              // strip chunks: f~^0 and phi history
   const T* __restrict__ tabx;
   const T* __restrict__ taby;
+  const T* __restrict__ uv;         // caller-supplied cell velocities, or nullptr
   Tiling tl;
   double shift, kth;   // stored = feq - shift S (dt/2: f~ of T2, dt/4: f^ of T3S3)
 };
+
+// caller-supplied cell velocities (FP64, u plane then v plane) into the state
+// in its precision
+template <typename T>
+__global__ __launch_bounds__(256) void velocity_store_kernel(const double* __restrict__ in,
+                                                             T* __restrict__ out, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = T(in[j]);
+}
 
 // f~^0 = feq(phi0, u(x,0)) - (dt/2) S^0 with d(phi u)/dt = 0
 template <typename T>
@@ -863,13 +919,18 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
                     ((P(1, 1) - P(-1, 1)) + (P(1, -1) - P(-1, -1))) / 12.0;
   const double gy = (P(0, 1) - P(0, -1)) / 3.0 +
                     ((P(1, 1) - P(1, -1)) + (P(-1, 1) - P(-1, -1))) / 12.0;
-  const double gm = sqrt(gx * gx + gy * gy);
-  const double den = gm > 1e-12 ? gm : 1e-12;
+  const double den = sqrt(gx * gx + gy * gy + NORMAL_EPS * NORMAL_EPS);
   const double th = a.kth * pC * (1.0 - pC);
   const double nvx = gx / den, nvy = gy / den;
-  const double u = (double)a.tabx[2 * x + 1] * (double)a.taby[2 * y + 1];
-  const double v = (double)a.tabx[(2 * nx + 2) + 2 * x + 1] *
-                   (double)a.taby[(2 * ny + 2) + 2 * y + 1];
+  double u, v;
+  if (a.uv) {
+    const int64_t o = (int64_t)y * nx + x;
+    u = (double)a.uv[o];
+    v = (double)a.uv[(int64_t)nx * ny + o];
+  } else {
+    u = (double)a.tabx[2 * x + 1] * (double)a.taby[2 * y + 1];
+    v = (double)a.tabx[(2 * nx + 2) + 2 * x + 1] * (double)a.taby[(2 * ny + 2) + 2 * y + 1];
+  }
 #pragma unroll
   for (int i = 0; i < 9; i++) {
     const double eu = ex(i) * u + ey(i) * v;
@@ -904,6 +965,16 @@ __global__ __launch_bounds__(256) void phi_kernel(const T* __restrict__ buf, Til
 #pragma unroll
   for (int i = 1; i < 9; i++) s += stored_f(buf[o + i * OWN], i, f0, hdr);
   out[(int64_t)y * tl.nx + x] = s;
+}
+
+// the phi history plane (phi^{n-1} of a state at step n), as stored
+template <typename T>
+__global__ __launch_bounds__(256) void history_kernel(const T* __restrict__ buf, Tiling tl,
+                                                      T* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= tl.nx || y >= tl.ny) return;
+  out[(int64_t)y * tl.nx + x] = buf[tl.idx(9, y, x)];
 }
 
 template <typename T>
@@ -965,9 +1036,12 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
   }
 }
 
+// the total, to out (and out2); a non-finite total sets the state's sticky
+// status ENUMERIC
 static __global__ __launch_bounds__(64) void mass_final_kernel(const double* __restrict__ part,
                                                         double* __restrict__ out,
-                                                        double* __restrict__ out2) {
+                                                        double* __restrict__ out2,
+                                                        StateHeader* __restrict__ hdr) {
   if (threadIdx.x != 0) return;
   double s = 0.0, c = 0.0;
   for (int b = 0; b < MASS_BLOCKS; b++) {
@@ -977,6 +1051,7 @@ static __global__ __launch_bounds__(64) void mass_final_kernel(const double* __r
   const double m = s + c;
   *out = m;
   if (out2) *out2 = m;
+  if (!isfinite(m)) hdr->status = DUGKS_ENUMERIC;
 }
 
 // f~_i += w_i (M0 - M) / (nx ny)

@@ -2,6 +2,8 @@
 // single-grid and batch entry points (private to the library).
 #pragma once
 
+#include <math.h>
+
 #include <mutex>
 #include <vector>
 

@@ -194,6 +194,33 @@ def run_table(table: str, scheme: str, flags: int = 0) -> dict:
             for k, c in enumerate(CFLS)}
 
 
+# Printed values read as misprints (see the notes in tests/golden/paper_tables.json):
+# (table, scheme, CFL key, column) -> the corrected reading
+MISPRINTS = {("IX", "T2S3", "CFL0.5", 0.1): 9.55e-3,
+             ("III", "T3S3", "CFL0.25", 0.05): 1.09e-2}
+
+
+def compare(out: dict, golden: dict) -> dict:
+    """Ratio computed / printed of every entry of `out` (run_table results keyed
+    "table/scheme") against the printed tables: per key, (min, max, mean |r - 1|,
+    count)."""
+    res = {}
+    for key, tab in out.items():
+        table, scheme = key.split("/")
+        g = golden[table]
+        ratios = []
+        for cfl_key, row in tab.items():
+            for col, v in row.items():
+                c = float(col)
+                printed = MISPRINTS.get((table, scheme, cfl_key, c),
+                                        g[scheme][cfl_key][g["cols"].index(c)])
+                if v is not None and printed is not None:
+                    ratios.append(v / printed)
+        r = np.array(ratios)
+        res[key] = (float(r.min()), float(r.max()), float(np.mean(np.abs(r - 1))), len(r))
+    return res
+
+
 def main(argv=None) -> int:
     import argparse
     import json
@@ -202,6 +229,8 @@ def main(argv=None) -> int:
                                  "T3S3) on the GPU and print E_phi of every entry as JSON.")
     ap.add_argument("tables", nargs="*", default=["I", "II", "III", "IV", "V", "VIII", "IX"])
     ap.add_argument("--schemes", nargs="*", default=list(SCHEMES))
+    ap.add_argument("--compare", metavar="GOLDEN_JSON", default=None,
+                    help="also print the ratio computed / printed per table and scheme")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("the paper tables need a HIP device", file=sys.stderr)
@@ -212,6 +241,9 @@ def main(argv=None) -> int:
             out[f"{t}/{s}"] = run_table(t, s)
             print(f"table {t} {s} done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
+    if args.compare:
+        for key, (lo, hi, mean, n) in compare(out, json.load(open(args.compare))).items():
+            print(f"{key}: {lo:.3f}-{hi:.3f} ({mean:.3f}) over {n}", flush=True)
     return 0
 
 

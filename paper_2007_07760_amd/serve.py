@@ -7,7 +7,9 @@ its phi0 in device memory, and attaches it to one batch (include/dugks.h:
 one persistent kernel per step over every active grid, K-step hipGraph
 replays).  Grids leave the batch when they reach their own step count; their
 phi is copied to pinned host memory and the request completes when the copy
-has landed.  Requests that arrive while others are on the GPU join before
+has landed.  A grid whose state turns non-finite (the library's status
+DUGKS_ENUMERIC, from its first state or its per-step mass sum) is stopped by
+the batch and its request fails alone, with that status and no result.  Requests that arrive while others are on the GPU join before
 the next group of K steps.  The baseline runs the same requests one at a time, in arrival
 order, each with its own per-step launches (dugks_step).
 
@@ -119,6 +121,7 @@ class Result:
     cells: int
     steps: int
     phi: np.ndarray | None
+    status: int = C.OK       # C.ENUMERIC: the solve blew up; no result
 
     @property
     def latency(self) -> float:
@@ -147,6 +150,8 @@ class Server:
         self.pool = Pool(budget_bytes, self.device)
         self._ctr = [torch.zeros(2 * self.slots, dtype=torch.int64, pin_memory=True)
                      for _ in range(2)]
+        self._stat = [torch.zeros(self.slots, dtype=torch.int32, pin_memory=True)
+                      for _ in range(2)]
         self._ev = [torch.cuda.Event(), torch.cuda.Event()]
 
     def run(self, trace: list, keep_phi=(), progress=None) -> list[Result]:
@@ -200,6 +205,7 @@ class Server:
                     j = rounds & 1
                     self.batch.step(self.K, graph_steps=self.K)
                     self.batch.steps_async(self._ctr[j])
+                    self.batch.status_async(self._stat[j])
                     self._ev[j].record()
                     round_of[j] = rounds
                     rounds += 1
@@ -207,17 +213,27 @@ class Server:
                     if last is not None:
                         self._ev[last].synchronize()
                         ctr = self._ctr[last].numpy().reshape(self.slots, 2)
+                        stat = self._stat[last].numpy()
                         for slot in [s for s, jb in active.items()
                                      if jb.first_round <= round_of[last]
-                                     and ctr[s, 0] >= jb.req["steps"]]:
+                                     and (ctr[s, 0] >= jb.req["steps"] or stat[s] != C.OK)]:
                             jb = active.pop(slot)
-                            jb.solver.step_index = jb.req["steps"]
-                            phi = jb.solver.phi()
-                            host = torch.empty(phi.shape, dtype=phi.dtype, pin_memory=True)
-                            host.copy_(phi, non_blocking=True)
-                            ev = torch.cuda.Event()
-                            ev.record()
-                            finishing.append((jb, host, ev))
+                            if stat[slot] != C.OK:
+                                # blown up: the batch has stopped it; fail it alone
+                                r = jb.req
+                                results[r["id"]] = Result(
+                                    r["id"], r["arrival"], jb.admitted,
+                                    time.perf_counter() - t0, r["nx"] * r["ny"],
+                                    int(ctr[slot, 0]), None, int(stat[slot]))
+                            else:
+                                jb.solver.step_index = jb.req["steps"]
+                                phi = jb.solver.phi()
+                                host = torch.empty(phi.shape, dtype=phi.dtype,
+                                                   pin_memory=True)
+                                host.copy_(phi, non_blocking=True)
+                                ev = torch.cuda.Event()
+                                ev.record()
+                                finishing.append((jb, host, ev))
                             self.batch.clear(slot)
                             free.append(slot)
                             self.pool.release(jb.off, jb.nbytes)
@@ -283,6 +299,7 @@ def run_fifo(trace: list, keep_phi=(), device="cuda", progress=None) -> list[Res
 
 
 def summary(results: list[Result]) -> dict:
+    failed = sum(1 for r in results if r.status != C.OK)
     lat = np.array([r.latency for r in results])
     lus = sum(r.cells * r.steps for r in results)
     t_first = min(r.arrival for r in results)
@@ -290,7 +307,7 @@ def summary(results: list[Result]) -> dict:
     return dict(requests=len(results), mlups=lus / (t_last - t_first) / 1e6,
                 makespan_s=t_last - t_first, p50_s=float(np.percentile(lat, 50)),
                 p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
-                lattice_updates=int(lus))
+                lattice_updates=int(lus), failed=failed)
 
 
 def main(argv=None) -> int:

@@ -46,12 +46,23 @@ class Solver:
     def stream() -> int:
         return torch.cuda.current_stream().cuda_stream
 
-    def init(self, phi0) -> "Solver":
-        phi0 = torch.as_tensor(np.ascontiguousarray(phi0, dtype=np.float64)
-                               if isinstance(phi0, np.ndarray) else phi0)
-        phi0 = phi0.to(device=self.device, dtype=torch.float64).contiguous()
+    @staticmethod
+    def _device_f64(a, device) -> torch.Tensor:
+        a = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)
+                            if isinstance(a, np.ndarray) else a)
+        return a.to(device=device, dtype=torch.float64).contiguous()
+
+    def init(self, phi0, uv=None) -> "Solver":
+        """First state from phi0 ([ny][nx]); `uv` ([2][ny][nx]: u, then v, at
+        the cell centres) for plans with caller-supplied velocities."""
+        phi0 = self._device_f64(phi0, self.device)
         assert tuple(phi0.shape) == (self.ny, self.nx)
-        C.dugks_init(self.plan, self.state.data_ptr(), phi0.data_ptr(), self.stream())
+        uvp = None
+        if uv is not None:
+            uv = self._device_f64(uv, self.device)
+            assert tuple(uv.shape) == (2, self.ny, self.nx)
+            uvp = uv.data_ptr()
+        C.dugks_init(self.plan, self.state.data_ptr(), phi0.data_ptr(), uvp, self.stream())
         self.step_index = 0
         return self
 
@@ -92,6 +103,20 @@ class Solver:
         C.dugks_distributions(self.plan, self.state.data_ptr(), self.step_index,
                               out.data_ptr(), self.stream())
         return out
+
+    def history(self) -> torch.Tensor:
+        """The stored phi of the previous step (the history plane)."""
+        out = torch.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+        C.dugks_history(self.plan, self.state.data_ptr(), self.step_index, out.data_ptr(),
+                        self.stream())
+        return out
+
+    def status(self) -> int:
+        """The state's sticky status (OK, or ENUMERIC after a non-finite total);
+        waits for the stream."""
+        st = torch.empty(1, dtype=torch.int32, device=self.device)
+        C.dugks_state_status(self.plan, self.state.data_ptr(), st.data_ptr(), self.stream())
+        return int(st.item())
 
     def mass(self) -> float:
         C.dugks_mass(self.plan, self.state.data_ptr(), self.step_index,

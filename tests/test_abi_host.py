@@ -68,10 +68,24 @@ def test_plan_create_valid(lib, recon, prec):
     (dict(vel_param=(math.nan, 0.0)), C.EINVAL), (dict(flags=4), C.EINVAL),
     (dict(tile_rows=-1), C.EINVAL),
     (dict(vel_kind=C.VEL_SINGLE_VORTEX, vel_param=(0.05, 0.0)), C.EINVAL),
-    (dict(vel_kind=C.VEL_ARRAYS), C.EUNSUPPORTED),
 ])
 def test_plan_create_rejects(lib, bad, code):
     assert C.dugks_plan_create_status(_p(**bad)) == code
+
+
+def test_velocity_arrays_plan(lib):
+    """Caller-supplied velocities: the plan is valid, its state holds the two
+    planes on top of the analytic kind's, and dugks_init refuses it without
+    them (before touching the device)."""
+    plain = C.dugks_plan_create(_p(nx=64, ny=48))
+    arr = C.dugks_plan_create(_p(nx=64, ny=48, vel_kind=C.VEL_ARRAYS))
+    try:
+        extra = C.dugks_state_bytes(arr) - C.dugks_state_bytes(plain)
+        assert 2 * 64 * 48 * 8 <= extra < 2 * 64 * 48 * 8 + 512
+        assert lib.dugks_init(arr, 4096, 4096, None, None) == C.EINVAL
+    finally:
+        C.dugks_plan_destroy(plain)
+        C.dugks_plan_destroy(arr)
 
 
 def test_plan_create_edge_values(lib):
@@ -84,9 +98,14 @@ def test_plan_create_edge_values(lib):
 def test_calls_reject_null_before_the_device(lib):
     plan = C.dugks_plan_create(_p())
     try:
-        assert lib.dugks_init(None, None, None, None) == C.EINVAL
-        assert lib.dugks_init(plan, None, None, None) == C.EINVAL
-        assert lib.dugks_init(plan, 256 * 1000 + 8, 4096, None) == C.EINVAL  # misaligned
+        assert lib.dugks_init(None, None, None, None, None) == C.EINVAL
+        assert lib.dugks_init(plan, None, None, None, None) == C.EINVAL
+        assert lib.dugks_init(plan, 256 * 1000 + 8, 4096, None, None) == C.EINVAL  # misaligned
+        assert lib.dugks_history(plan, None, 0, 4096, None) == C.EINVAL
+        assert lib.dugks_history(plan, 4096, -1, 4096, None) == C.EINVAL
+        assert lib.dugks_state_status(plan, 4096, None, None) == C.EINVAL
+        assert lib.dugks_state_status(None, 4096, 4096, None) == C.EINVAL
+        assert lib.dugks_batch_status(None, 4096, None) == C.EINVAL
         assert lib.dugks_step(plan, None, 0, 1, None) == C.EINVAL
         assert lib.dugks_step(plan, 4096, -1, 1, None) == C.EINVAL
         assert lib.dugks_step(plan, 4096, 0, -1, None) == C.EINVAL

@@ -214,3 +214,78 @@ def test_batch_scheme_must_match(lib):
     t3 = Solver(40, 32, 0.02, 4.0, 0.5, recon=lib.UPWIND3, scheme=lib.T3S3).init(_phi0(40, 32, 0))
     with pytest.raises(lib.DugksError):
         b2.set(0, t3, 5)
+
+
+@pytest.mark.parametrize("precision,flags", [(1, 2), (0, 0)])
+def test_batch_stops_a_blown_up_slot(lib, precision, flags):
+    """A grid whose first state is non-finite is stopped after its first batch
+    step with status ENUMERIC; the other grids run on, bitwise as alone."""
+    import torch
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+    print(f"case batch blow-up prec={precision} flags={flags}", flush=True)
+    b = Batch(4, precision, lib.UPWIND3, flags)
+    good = []
+    for k in (0, 1):
+        s = _solver(lib, GRIDS[k], k, precision, flags, lib.UPWIND3)
+        b.set(k, s, 16)
+        good.append(s)
+    nx, ny, kind, prm = GRIDS[3]
+    phi0 = _phi0(nx, ny, 3)
+    phi0[5, 7] = np.nan
+    bad = Solver(nx, ny, 0.01, 4.0, 0.5, recon=lib.UPWIND3, precision=precision,
+                 vel_kind=kind, vel_param=prm, flags=flags).init(phi0)
+    b.set(2, bad, 16)
+    b.commit()
+    b.step(16, graph_steps=4)
+    st = b.sync()
+    status = b.status()
+    assert list(status[:3]) == [lib.OK, lib.OK, lib.ENUMERIC]
+    assert [int(x) for x in st[:3, 0]] == [16, 16, 1] and int(st[2, 1]) == 1
+    for k, s in enumerate(good):
+        ref = _alone(lib, GRIDS[k], k, precision, flags, lib.UPWIND3, 16)
+        assert torch.equal(s.distributions(), ref.distributions()), k
+    # a slot attached again after the failure starts with a clean status
+    b.clear(2)
+    c = _solver(lib, GRIDS[4], 4, precision, flags, lib.UPWIND3)
+    b.set(2, c, 4)
+    b.commit()
+    assert b.status()[2] == lib.OK
+    b.step(4, graph_steps=0)
+    assert b.status()[2] == lib.OK and int(b.sync()[2, 0]) == 4
+
+
+def test_batch_fused_correction_catches_a_blow_up_mid_run(lib):
+    """FP32 with the fused correction: a grid whose state turns non-finite
+    during the run is stopped at the next batch step by its own mass sum."""
+    import torch
+    from paper_2007_07760_amd.batch import Batch
+    print("case batch blow-up mid-run", flush=True)
+    b = Batch(2, lib.F32, lib.UPWIND3, lib.FLAG_MASS_FIX)
+    a = _solver(lib, GRIDS[1], 1, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3)
+    z = _solver(lib, GRIDS[3], 3, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3)
+    b.set(0, a, 30)
+    b.set(1, z, 30)
+    b.commit()
+    b.step(6, graph_steps=0)
+    assert list(b.status()[:2]) == [lib.OK, lib.OK]
+    n = z.state.numel()
+    z.state[n // 4:3 * n // 4].view(torch.float32).fill_(float("nan"))
+    b.step(24, graph_steps=4)
+    st = b.sync()
+    assert list(b.status()[:2]) == [lib.OK, lib.ENUMERIC]
+    assert int(st[0, 0]) == 30 and int(st[1, 0]) == 7
+    ref = _alone(lib, GRIDS[1], 1, lib.F32, lib.FLAG_MASS_FIX, lib.UPWIND3, 30)
+    assert torch.equal(a.distributions(), ref.distributions())
+
+
+def test_batch_refuses_velocity_arrays(lib):
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+    b = Batch(2, lib.F64, lib.UPWIND3, 0)
+    uv = np.zeros((2, 32, 40))
+    s = Solver(40, 32, 0.01, 4.0, 0.5, recon=lib.UPWIND3, vel_kind=lib.VEL_ARRAYS).init(
+        _phi0(40, 32, 0), uv)
+    with pytest.raises(lib.DugksError) as e:
+        b.set(0, s, 5)
+    assert e.value.code == lib.EUNSUPPORTED

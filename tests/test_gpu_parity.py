@@ -1,16 +1,20 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bar: FP64 relative L-inf <= 1e-12 on phi and on the 9 distribution planes.
-The two sides differ only in rounding (FMA contraction on the GPU, order of
-the stencil sums, 1-ulp sin/cos).  The method itself amplifies rounding where
-grad(phi) vanishes while theta does not (the normal grad/|grad| flips at the
-extrema of small over- and undershoots), so on long or sharp runs two correct
-roundings part by more than 1e-12.  Each case therefore also advances a twin
-of the oracle built with FMA contraction -- the same source, another rounding
--- and the bar is max(1e-12, 100 x twin divergence): strict while the method
-is well conditioned, and after an ill-conditioned event within two orders of
-magnitude of what rounding alone does to it (the size of an event differs
-between rounding realizations by about one order of magnitude).
+Bar: FP64 relative L-inf <= 1e-12 on phi and on the 9 distribution planes,
+two ways.
+  - Trajectories: the GPU and the oracle advance the same first state side by
+    side and are compared at several steps.  With the normal of Eq. (2)
+    regularised (n = g / sqrt(|g|^2 + 1e-8)) the method is well conditioned:
+    the oracle and its FMA-contracted twin (the same source, another rounding)
+    stay within rounding of each other over whole runs, and so must the GPU.
+  - One step from the GPU's own state: at checkpoints of full-length runs the
+    GPU state (f~^n and the phi^{n-1} history plane, dugks_distributions and
+    dugks_history) is handed to the oracle, which takes step n once; the GPU's
+    step n must agree with it.  This checks every step's arithmetic at states
+    deep into long runs, where running the oracle the whole way would take
+    too long.
+The FMA twin's divergence is printed beside each trajectory comparison as a
+diagnostic of conditioning; it is not part of any bar.
 """
 import math
 
@@ -40,9 +44,10 @@ def _rel_linf(a, b):
 
 
 class _Twin:
-    """The oracle and its FMA-contracted twin, advanced together."""
+    """The oracle, and optionally its FMA-contracted twin, advanced together."""
 
     def __init__(self, orc, p, phi0, twin=True):
+        self.p = p
         self.o = orc.State(p, phi0)
         self.t = orc.State(p, phi0, variant="fma") if twin else None
         self.tf = self.o.tf
@@ -57,21 +62,22 @@ class _Twin:
     def phi(self):
         return self.o.phi()
 
-    def bar(self):
+    def twin_divergence(self):
         if self.t is None:
-            return TOL64, 0.0
-        tw = max(_rel_linf(self.t.tf, self.o.tf), _rel_linf(self.t.phi(), self.o.phi()))
-        return max(TOL64, 100.0 * tw), tw
+            return float("nan")
+        return max(_rel_linf(self.t.tf, self.o.tf), _rel_linf(self.t.phi(), self.o.phi()))
 
 
 def _pair(gpu, orc, nx, ny, M, W, cfl, recon, kind, prm, phi0, tile_rows=0,
-          precision=0, flags=0, twin=True, scheme=0):
+          precision=0, flags=0, twin=True, scheme=0, uv=None):
     print(f"case nx={nx} ny={ny} recon={recon} vel={kind} prm={prm} tile={tile_rows} "
           f"prec={precision} scheme={scheme}", flush=True)
     g = gpu(nx, ny, M, W, cfl, recon=recon, precision=precision, vel_kind=kind,
-            vel_param=prm, flags=flags, tile_rows=tile_rows, scheme=scheme).init(phi0)
+            vel_param=prm, flags=flags, tile_rows=tile_rows, scheme=scheme).init(phi0, uv)
     p = orc.Params(nx, ny, M, W, cfl, recon, kind, prm, dtphiu_zero=bool(flags & 1),
                    scheme=scheme)
+    if uv is not None:
+        p.u_arr, p.v_arr = uv[0], uv[1]
     return g, _Twin(orc, p, phi0, twin)
 
 
@@ -85,10 +91,34 @@ def _compare(g, o):
 
 def _check(g, o, label=""):
     ef, ep = _compare(g, o)
-    tol, tw = o.bar()
-    print(f"{label}: f {ef:.2e} phi {ep:.2e} twin {tw:.2e} bar {tol:.1e}", flush=True)
-    assert ef <= tol and ep <= tol, (label, ef, ep, tw)
+    tw = o.twin_divergence()
+    print(f"{label}: f {ef:.2e} phi {ep:.2e} (oracle vs FMA twin {tw:.2e})", flush=True)
+    assert ef <= TOL64 and ep <= TOL64, (label, ef, ep, tw)
     return ef, ep, tw
+
+
+def one_step_check(g, orc, p, label=""):
+    """Hand the GPU state at step n to the oracle, take step n on both sides and
+    compare the new distributions and the new history plane (phi^n)."""
+    n = g.step_index
+    f = g.distributions().cpu().numpy().astype(np.float64)
+    h = g.history().cpu().numpy().astype(np.float64)
+    f1, h1 = orc.step(p, n, f, h)
+    g.step(1)
+    ef = _rel_linf(g.distributions().cpu().numpy().astype(np.float64), f1)
+    eh = _rel_linf(g.history().cpu().numpy().astype(np.float64), h1)
+    print(f"{label} one step from GPU state at n={n}: f {ef:.2e} history {eh:.2e}",
+          flush=True)
+    assert ef <= TOL64 and eh <= TOL64, (label, n, ef, eh)
+    return ef, eh
+
+
+def checkpoints_run(g, orc, p, marks, label=""):
+    """Advance the GPU to each mark n and check step n there against the oracle
+    (so the GPU ends at marks[-1] + 1)."""
+    for n in marks:
+        g.step(n - g.step_index)
+        one_step_check(g, orc, p, label)
 
 
 def test_init_matches_oracle(gpu, orc):
@@ -100,20 +130,19 @@ def test_init_matches_oracle(gpu, orc):
 
 
 def test_c1_full_period(gpu, orc):
-    """64^2 FP64 central-2 translating circle over one period (3200 steps);
-    strict 1e-12 through step 1600, conditioning-aware after the first
-    ill-conditioned event (~step 1750), plus the L2 error of Eq. (41)."""
+    """64^2 FP64 central-2 translating circle over one period (3200 steps):
+    the whole trajectory within 1e-12 of the oracle, the L2 error of Eq. (41),
+    and one step from the GPU's own state at steps 0, 1000, 1750, 2500 and
+    3199 of a second run."""
     w = I.workload("c1")
     g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                  w["recon"], w["vel_kind"], w["vel_param"], w["phi0"])
     done = 0
-    for target in (1, 10, 100, 1600, 3200):
+    for target in (1, 10, 100, 1600, 1750, 2500, 3200):
         g.step(target - done)
         o.run(target - done)
         done = target
-        ef, ep, tw = _check(g, o, f"c1 step {target}")
-        if target <= 1600:
-            assert ef < TOL64 and ep < TOL64
+        _check(g, o, f"c1 step {target}")
         if target == 1600:
             # half a period: u t = (32, 32) cells, so the exact answer is phi0
             # rolled by 32 cells along both axes (Eq. 41 against it)
@@ -128,7 +157,10 @@ def test_c1_full_period(gpu, orc):
     eg = orc.e_phi(g.phi().cpu().numpy(), w["phi0"])
     eo = orc.e_phi(o.phi(), w["phi0"])
     print(f"E_phi gpu {eg:.6e} oracle {eo:.6e}", flush=True)
-    assert eg == pytest.approx(eo, rel=1e-3)
+    assert eg == pytest.approx(eo, rel=1e-9)
+    g2, _ = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                  w["recon"], w["vel_kind"], w["vel_param"], w["phi0"], twin=False)
+    checkpoints_run(g2, orc, o.p, (0, 1000, 1750, 2500, 3199), "c1")
 
 
 KINDS = [
@@ -230,15 +262,26 @@ def test_tile_shape_invariance_bitwise(gpu):
 
 
 def test_c2_rotation_first_steps(gpu, orc):
+    """256^2 slotted disk, upwind-3: the first 500 steps of the turn side by
+    side with the oracle."""
     w = I.workload("c2")
     g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
                  w["recon"], w["vel_kind"], w["vel_param"], w["phi0"])
     done = 0
-    for target in (1, 100, 200, 500):     # the first 500 steps of the turn
+    for target in (1, 100, 200, 500):
         g.step(target - done)
         o.run(target - done)
         done = target
         _check(g, o, f"c2 step {target}")
+
+
+def test_c2_full_turn_checkpoints(gpu, orc):
+    """The whole turn (8000 steps) on the GPU, one step from its own state
+    checked every 1000 steps."""
+    w = I.workload("c2")
+    g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                 w["recon"], w["vel_kind"], w["vel_param"], w["phi0"], twin=False)
+    checkpoints_run(g, orc, o.p, (1000, 2000, 3000, 4000, 5000, 6000, 7000, 7999), "c2")
 
 
 def test_c3_single_vortex_central4(gpu, orc):
@@ -252,17 +295,27 @@ def test_c3_single_vortex_central4(gpu, orc):
             _check(g, o, f"c3 recon {recon} step {target}")
 
 
+@pytest.mark.parametrize("recon", [2, 1])
+def test_c3_full_run_checkpoints(gpu, orc, recon):
+    """512^2 single vortex to maximum stretch and back (12800 steps), central-4
+    and upwind-3: one step from the GPU's own state every 2000 steps."""
+    w = I.workload("c3_512")
+    g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                 recon, w["vel_kind"], w["vel_param"], w["phi0"], twin=False)
+    checkpoints_run(g, orc, o.p, (2000, 4000, 6000, 8000, 10000, 12000, 12799),
+                    f"c3 recon {recon}")
+
+
 def test_mass_conservation_fp64(gpu):
     w = I.workload("c2")
     g = gpu(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"], recon=1,
             vel_kind=w["vel_kind"], vel_param=w["vel_param"]).init(w["phi0"])
     m0 = g.mass0()
     assert g.mass() == pytest.approx(m0, rel=1e-14)
-    # conservative in exact arithmetic; in FP64 the collision coefficients and
-    # weights sum to 1 only to an ulp, a systematic ~2e-16 per step
-    steps = 500
-    g.step(steps)
-    assert abs(g.mass() - m0) / m0 < 5e-16 * steps
+    # conservative in exact arithmetic (the relaxation and source move no
+    # mass, the fluxes cancel pairwise); FP64 rounding only
+    g.step(500)
+    assert abs(g.mass() - m0) / m0 < 1e-13
 
 
 def test_headline_size_two_steps(gpu, orc):
@@ -280,3 +333,92 @@ def test_headline_size_two_steps(gpu, orc):
             o = o2.run(2)
         g.step(2)
         _check(g, o, f"h1 step 2 tile {tile}")
+
+
+# ------------------------------------------- caller-supplied velocity arrays
+def _array_field(nx, ny, seed):
+    """A smooth periodic steady field at the cell centres (a rotation cell and
+    a shear, |u| <= ~0.06), not separable in x and y."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    a, b = rng.uniform(0.02, 0.04, size=2)
+    ph = rng.uniform(0, 2 * np.pi)
+    u = -a * np.sin(2 * np.pi * X + ph) * np.cos(2 * np.pi * Y) + b * np.sin(2 * np.pi * Y)
+    v = a * np.cos(2 * np.pi * X + ph) * np.sin(2 * np.pi * Y) + 0.5 * b * np.cos(4 * np.pi * X)
+    return np.stack([u, v])
+
+
+@pytest.mark.parametrize("recon", [0, 1, 2])
+def test_velocity_arrays_ragged(gpu, orc, recon):
+    """Velocity given as cell arrays (face = mean of the two cells) on a ragged
+    100 x 72 grid, 16-row tiles, every reconstruction, FP64."""
+    nx, ny = 100, 72
+    phi0 = I.random_circles(nx, ny, 5, 6.0, 14.0, 4.0, seed=40 + recon)
+    uv = _array_field(nx, ny, seed=recon)
+    g, o = _pair(gpu, orc, nx, ny, 0.01, 4.0, 0.6, recon, 4, (), phi0, tile_rows=16, uv=uv)
+    for steps in (1, 2, 37):
+        g.step(steps)
+        o.run(steps)
+        _check(g, o, f"arrays +{steps}")
+
+
+def test_velocity_arrays_equal_analytic_field(gpu):
+    """A uniform field passed as arrays runs the same arithmetic as the
+    uniform kind (face means of equal values are exact): bitwise equal."""
+    nx, ny = 130, 90
+    phi0 = I.random_circles(nx, ny, 6, 5.0, 15.0, 4.0, seed=5)
+    uv = np.stack([np.full((ny, nx), 0.03), np.full((ny, nx), -0.02)])
+    for prec in (0, 1):
+        a = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, precision=prec, vel_kind=0,
+                vel_param=(0.03, -0.02)).init(phi0).step(30)
+        b = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, precision=prec, vel_kind=4).init(phi0, uv)
+        b.step(30)
+        da, db = a.distributions().cpu().numpy(), b.distributions().cpu().numpy()
+        print(f"arrays vs uniform, precision {prec}: max diff {np.max(np.abs(da - db)):.2e}",
+              flush=True)
+        assert np.max(np.abs(da - db)) <= (1e-15 if prec == 0 else 1e-7)
+
+
+def test_velocity_arrays_headline_size(gpu, orc):
+    """4096^2 with a cell-array field, the benchmarked circles, two steps."""
+    w = I.workload("h1")
+    uv = _array_field(w["nx"], w["ny"], seed=7)
+    g, o = _pair(gpu, orc, w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"],
+                 w["recon"], 4, (), w["phi0"], twin=False, uv=uv)
+    g.step(2)
+    o.run(2)
+    _check(g, o, "arrays 4096^2 step 2")
+
+
+# ------------------------------------------------------------ blow-up status
+def test_nonfinite_state_reports_enumeric(gpu):
+    """A NaN in phi0 sets the sticky status at dugks_init; a finite state
+    keeps DUGKS_OK, also with the fused correction every step."""
+    from paper_2007_07760_amd import _lib as C
+    nx, ny = 96, 64
+    phi0 = I.random_circles(nx, ny, 4, 6.0, 14.0, 4.0, seed=2)
+    bad = phi0.copy()
+    bad[10, 20] = np.nan
+    for prec, flags in ((0, 0), (1, C.FLAG_MASS_FIX)):
+        ok = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, precision=prec, flags=flags,
+                 vel_kind=0, vel_param=(0.02, 0.01)).init(phi0).step(20)
+        assert ok.status() == C.OK
+        nb = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, precision=prec, flags=flags,
+                 vel_kind=0, vel_param=(0.02, 0.01)).init(bad)
+        assert nb.status() == C.ENUMERIC
+        nb.step(5)
+        assert nb.status() == C.ENUMERIC
+    # a state that turns non-finite during the run: dugks_mass sets it
+    nb = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, vel_kind=0, vel_param=(0.02, 0.01)).init(phi0)
+    nb.step(3)
+    assert nb.status() == C.OK
+    # poison the middle half of the state, which takes rows of both ping-pong
+    # buffers, as a blow-up would leave them
+    import torch
+    n = nb.state.numel()
+    nb.state[n // 4:3 * n // 4].view(torch.float64).fill_(float("nan"))
+    with pytest.raises(C.DugksError):
+        nb.mass()
+    assert nb.status() == C.ENUMERIC

@@ -58,3 +58,33 @@ def test_serve_rejects_oversized(serve):
     srv = serve.Server(slots=2, budget_bytes=64 << 10)
     with pytest.raises(ValueError):
         srv.run(trace)
+
+
+def test_serve_fails_only_the_blown_up_request(serve, monkeypatch):
+    """A request whose solve is non-finite (here: a NaN planted in its phi0)
+    fails alone with status ENUMERIC; every other request completes and equals
+    its alone run."""
+    from paper_2007_07760_amd import _lib as C
+    trace = _trace()[:6]
+    victim = trace[2]["id"]
+    real = serve.request_phi0
+
+    def poisoned(req, device):
+        phi = real(req, device)
+        if req["id"] == victim:
+            phi[3, 4] = float("nan")
+        return phi
+
+    monkeypatch.setattr(serve, "request_phi0", poisoned)
+    print("case serve blow-up", flush=True)
+    srv = serve.Server(slots=3, budget_bytes=64 << 20, graph_steps=8)
+    res = srv.run(trace, keep_phi=[r["id"] for r in trace])
+    monkeypatch.setattr(serve, "request_phi0", real)
+    assert srv.pool.used == 0
+    for r, req in zip(res, trace):
+        if req["id"] == victim:
+            assert r.status == C.ENUMERIC and r.phi is None and r.steps < req["steps"]
+        else:
+            assert r.status == C.OK
+            assert np.array_equal(r.phi, serve.run_alone(req)), req["id"]
+    assert serve.summary(res)["failed"] == 1

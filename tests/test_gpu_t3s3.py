@@ -3,14 +3,14 @@
 The library runs each T3S3 step as two launches of the march kernel (faces
 at t + dt/6 from fbar+ at t, and at t + 3 dt/4 from fbar+ at t + dt/3); the
 oracle takes the paper's steps (i)-(iv) one full-grid pass at a time.  Same
-bar as the T2 parity tests: FP64 relative L-inf <= max(1e-12, 100 x the
-divergence of the FMA-contracted twin of the oracle).
+bar as the T2 parity tests: FP64 relative L-inf <= 1e-12, on trajectories
+and on single steps taken from the GPU's own state deep into long runs.
 """
 import numpy as np
 import pytest
 
 from paper_2007_07760_amd import inputs as I
-from test_gpu_parity import KINDS, TOL64, _check, _pair
+from test_gpu_parity import KINDS, TOL64, _check, _pair, checkpoints_run
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,21 @@ def test_t3s3_ragged_all_schemes(gpu, orc, recon, kind):
         g.step(steps)
         o.run(steps)
         _check(g, o, f"t3s3 ragged +{steps}")
+    checkpoints_run(g, orc, o.p, (400, 1500), "t3s3 ragged")
+
+
+def test_t3s3_slotted_disk_checkpoints(gpu, orc):
+    """The 256^2 slotted disk of the FP32 accuracy runs (upwind-3, M = 0.02 so
+    that dt = 0.5 < 12 tau): trajectory to step 200, then one step from the
+    GPU's own state every 1000 steps of a whole turn (8000 steps)."""
+    w = I.workload("c2")
+    g, o = _pair(gpu, orc, w["nx"], w["ny"], 0.02, w["width"], w["cfl"], w["recon"],
+                 w["vel_kind"], w["vel_param"], w["phi0"], scheme=1)
+    g.step(200)
+    o.run(200)
+    _check(g, o, "t3s3 c2 step 200")
+    checkpoints_run(g, orc, o.p, (1000, 2000, 3000, 4000, 5000, 6000, 7000, 7999),
+                    "t3s3 c2")
 
 
 @pytest.mark.parametrize("shape,tile", [((8, 8), 1), ((59, 13), 5), ((130, 11), 64)])
@@ -173,5 +188,4 @@ def test_t3s3_headline_size_two_steps(gpu, orc):
         if o is None:
             o = o2.run(2)
         g.step(2)
-        ef, ep, _ = _check(g, o, f"t3s3 h1 step 2 tile {tile}")
-        assert ef < TOL64 and ep < TOL64
+        _check(g, o, f"t3s3 h1 step 2 tile {tile}")

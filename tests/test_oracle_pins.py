@@ -290,3 +290,167 @@ def test_fourier_mode_decay_and_phase(orc, recon, vel):
     shift = (-np.angle(A)) % (2 * math.pi)
     want = (k * ux * t) % (2 * math.pi)
     assert abs(shift - want) < 1e-3 * k * ux * t
+
+
+# ------------------------------------------- prescribed velocity fields
+# The analytic kinds are pinned by properties the fields of Sec. III have,
+# not by their formulas: a swapped centre, a flipped sign, a wrong wavenumber
+# or time modulation each breaks one of them.
+def _vel(orc, p, x, y, t=0.0):
+    return np.array(orc.velocity(p, float(x), float(y), float(t)))
+
+
+def test_rotation_is_rigid_about_its_centre(orc):
+    """Rigid rotation (the Zalesak field of Sec. III.B, u = -w (y - yc),
+    v = w (x - xc)): at every point u is perpendicular to x - c, |u| = w |x - c|,
+    the sense is counter-clockwise for w > 0, and the field is steady.  The
+    centre is off the diagonal so that swapping its coordinates is caught."""
+    w, cx, cy = 0.003, 41.0, 17.0
+    p = orc.Params(96, 64, 0.01, 4.0, 0.5, 1, orc.VEL_ROTATION, (w, cx, cy))
+    rng = np.random.default_rng(21)
+    for x, y in rng.uniform(0.0, 96.0, size=(200, 2)):
+        u = _vel(orc, p, x, y)
+        r = np.array([x - cx, y - cy])
+        rr = float(np.hypot(*r))
+        assert abs(u @ r) <= 1e-13 * (1.0 + rr * rr * w)
+        assert float(np.hypot(*u)) == pytest.approx(w * rr, rel=1e-12, abs=1e-15)
+        assert r[0] * u[1] - r[1] * u[0] == pytest.approx(w * rr * rr, rel=1e-12, abs=1e-15)
+        assert np.array_equal(_vel(orc, p, x, y, 123.4), u)
+    assert np.array_equal(_vel(orc, p, cx, cy), np.zeros(2))
+
+
+def _div_ratio(orc, p, n, t=0.0):
+    """max |central-difference divergence| / max |du/dx| of the field sampled
+    at the cell centres of an n x n grid."""
+    c = np.arange(n) + 0.5
+    U = np.array([[_vel(orc, p, x, y, t) for x in c] for y in c])
+    dudx = 0.5 * (np.roll(U[..., 0], -1, axis=1) - np.roll(U[..., 0], 1, axis=1))
+    dvdy = 0.5 * (np.roll(U[..., 1], -1, axis=0) - np.roll(U[..., 1], 1, axis=0))
+    return float(np.max(np.abs(dudx + dvdy)) / np.max(np.abs(dudx)))
+
+
+def test_deformation_field_symmetries(orc):
+    """The smoothed deformation field of Sec. III.D (Eq. 45) on an L0 x L0
+    domain: divergence-free (the central-difference divergence is O(dx^2)
+    while each derivative is O(1)), both components change sign under a shift
+    by L0/4 along either axis and repeat after L0/2 (wavenumber 4 pi / L0), the
+    time factor cos(pi t / T_f) reverses the flow exactly at t -> T_f - t, and
+    the field vanishes at T_f / 2."""
+    n, u0, tf = 64, 0.04, 250.0
+    p = orc.Params(n, n, 0.01, 4.0, 0.5, 1, orc.VEL_DEFORMATION, (u0, tf))
+    # (k dx)^2 / 6 = 0.0064 for k = 4 pi / 64: the discrete divergence's size
+    assert _div_ratio(orc, p, n) < 0.01
+    rng = np.random.default_rng(22)
+    for x, y in rng.uniform(0.0, n, size=(100, 2)):
+        u = _vel(orc, p, x, y)
+        assert np.allclose(_vel(orc, p, x + n / 4, y), -u, atol=1e-15)
+        assert np.allclose(_vel(orc, p, x, y + n / 4), -u, atol=1e-15)
+        assert np.allclose(_vel(orc, p, x + n / 2, y + n / 2), u, atol=1e-15)
+        for t in (0.0, 17.0, 101.5):
+            assert np.allclose(_vel(orc, p, x, y, tf - t), -_vel(orc, p, x, y, t),
+                               atol=1e-15)
+        assert np.max(np.abs(_vel(orc, p, x, y, tf / 2))) < 1e-15
+    # the amplitude is U0: |v| = U0 where both cosines are +-1 (x = y = 0)
+    assert np.allclose(_vel(orc, p, 0.0, 0.0), [0.0, -u0], atol=1e-15)
+
+
+def test_single_vortex_field_symmetries(orc):
+    """The single vortex of the workload list: divergence-free on a square
+    grid, zero normal velocity on the cell edges x = 0 and y = 0 (so it is
+    periodic without a jump), reversed at t -> P - t by cos(pi t / P)."""
+    n, u0, per = 64, 0.05, 300.0
+    p = orc.Params(n, n, 0.01, 4.0, 0.5, 1, orc.VEL_SINGLE_VORTEX, (u0, per))
+    assert _div_ratio(orc, p, n) < 0.01
+    rng = np.random.default_rng(23)
+    for s in rng.uniform(0.0, n, size=20):
+        assert abs(_vel(orc, p, 0.0, s)[0]) < 1e-15
+        assert abs(_vel(orc, p, s, 0.0)[1]) < 1e-15
+        assert np.allclose(_vel(orc, p, s, 0.3 * n, per - 40.0),
+                           -_vel(orc, p, s, 0.3 * n, 40.0), atol=1e-15)
+
+
+def test_deformation_run_returns_to_its_start(orc):
+    """Sec. III.D: the interface stretches during the first half period and
+    is restored in the second.  On a 64^2 grid (circle R = L0/5 at the centre,
+    W = 4, U0 = 0.04, T_f = 640, upwind-3, C = 0.5) the field at T_f is much
+    closer to phi0 than at T_f / 2, and much closer than after the same time
+    in the same field held steady (no time factor): a reversal at another
+    time, or none, would not bring it back."""
+    n, tf = 64, 640.0
+    phi0 = I.tanh_circle(n, n, n / 2, n / 2, n / 5, 4.0)
+    p = orc.Params(n, n, 0.01, 4.0, 0.5, 1, orc.VEL_DEFORMATION, (0.04, tf))
+    s = orc.State(p, phi0).run(int(tf / 2 / 0.5))
+    mid = orc.e_phi(s.phi(), phi0)
+    s.run(int(tf / 2 / 0.5))
+    end = orc.e_phi(s.phi(), phi0)
+    steady = orc.Params(n, n, 0.01, 4.0, 0.5, 1, orc.VEL_DEFORMATION, (0.04, 1e12))
+    held = orc.e_phi(orc.State(steady, phi0).run(int(tf / 0.5)).phi(), phi0)
+    print(f"deformation 64^2: E_phi at T_f/2 {mid:.3e}, at T_f {end:.3e}, "
+          f"steady field {held:.3e}")
+    assert mid > 0.3 and end < 0.2 * mid and held > 5 * end
+
+
+# ------------------------------------- X4: run-level isotropy (Sec. III.A)
+def _radius_profile(phi, cx, cy, nang=64, ds=0.05):
+    """Radius of the phi = 1/2 contour along nang rays from (cx, cy),
+    bilinear interpolation between cell centres."""
+    ny, nx = phi.shape
+    out = []
+    for k in range(nang):
+        a = 2 * math.pi * k / nang
+        prev = None
+        for s in np.arange(0.0, min(nx, ny) / 2 - 1, ds):
+            x = cx + s * math.cos(a) - 0.5
+            y = cy + s * math.sin(a) - 0.5
+            i, j = int(math.floor(x)), int(math.floor(y))
+            fx, fy = x - i, y - j
+            v = ((1 - fx) * (1 - fy) * phi[j % ny, i % nx] + fx * (1 - fy) * phi[j % ny, (i + 1) % nx]
+                 + (1 - fx) * fy * phi[(j + 1) % ny, i % nx] + fx * fy * phi[(j + 1) % ny, (i + 1) % nx])
+            if prev is not None and prev >= 0.5 > v:
+                out.append(s - ds + ds * (prev - 0.5) / (prev - v))
+                break
+            prev = v
+    return np.array(out)
+
+
+def _cos4(r):
+    ang = 2 * np.pi * np.arange(len(r)) / len(r)
+    return float(2 * np.mean(r * np.cos(4 * ang)))
+
+
+def test_circle_stays_round_with_isotropic_normal(orc):
+    """Sec. III.A (Fig. 4 and the text before it): with isotropic differences
+    for grad(phi) in the normal of Eq. (2) a circle keeps its shape, with
+    axis-aligned two-point differences it turns diamond-shaped.  A circle at
+    rest (R = 16, W = 4, M = 0.1, 64^2, upwind-3) is run for 6000 steps; the
+    cos(4 theta) harmonic of its phi = 1/2 radius stays below 0.03 cells with
+    the oracle's normal, and exceeds 0.08 cells in a test-only build of the
+    oracle with the two-point normal planted in it."""
+    n = 64
+    phi0 = I.tanh_circle(n, n, n / 2, n / 2, 16.0, 4.0)
+    p = orc.Params(n, n, 0.1, 4.0, 0.5, 1, orc.VEL_UNIFORM, (0.0, 0.0))
+    iso = _radius_profile(orc.State(p, phi0).run(6000).phi(), n / 2, n / 2)
+    ani = _radius_profile(orc.State(p, phi0, variant="aniso").run(6000).phi(), n / 2, n / 2)
+    print(f"cos 4 theta of the radius: isotropic {_cos4(iso):.4f}, two-point {_cos4(ani):.4f}")
+    assert len(iso) == 64 and len(ani) == 64
+    assert abs(_cos4(iso)) < 0.03
+    assert abs(_cos4(ani)) > 0.08
+    assert np.ptp(iso) < 0.05 < np.ptp(ani)
+
+
+# ------------------------------------------- conditioning of the normal (R11)
+def test_regularised_normal_keeps_long_runs_well_conditioned(orc):
+    """Eq. (2) is singular where grad(phi) vanishes; the reading
+    n = g / sqrt(|g|^2 + 1e-8) makes n continuous there.  Then two roundings of
+    the same arithmetic -- the oracle and its FMA-contracted build -- stay
+    within rounding of each other over the whole 64^2 translation period
+    (3200 steps); with the bare g / max(|g|, 1e-12) they parted by 7e-5 in phi
+    after the first sign change of g at an overshoot's extremum."""
+    w = I.workload("c1")
+    p = orc.Params(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"], w["recon"],
+                   w["vel_kind"], w["vel_param"])
+    a = orc.State(p, w["phi0"]).run(3200)
+    b = orc.State(p, w["phi0"], variant="fma").run(3200)
+    d = float(np.max(np.abs(a.tf - b.tf)) / np.max(np.abs(a.tf)))
+    print(f"oracle vs FMA build after 3200 steps: {d:.2e}")
+    assert d < 1e-13
