@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--only-batch", action="store_true",
                     help="the batched section alone (profiling runs)")
     ap.add_argument("--no-t3s3", action="store_true")
+    ap.add_argument("--no-t2s5", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32"], default=None,
@@ -228,6 +229,34 @@ def bench_t3s3(w, steps, warmup, tile_rows):
                      "mass_correction": "fused, every step",
                      "relative_mass_drift": float(f"{drift:.3g}"), "tile_rows": rows32,
                      "tile_source": source32, "bytes_per_lu": WORDS_PER_LU_T3S3 * 4}}
+
+
+def bench_t2s5(w, steps, warmup):
+    """DUGKS-T2S5 (the fifth-order reconstruction, one fused kernel per step
+    like T2S3) on the headline field, FP64 and FP32 with the fused mass
+    correction; the same 160 / 80 B of algorithmic traffic per update."""
+    import torch
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd.solver import Solver
+    out = {}
+    lus = w["nx"] * w["ny"]
+    for name, prec, flags in (("f64", C.F64, 0), ("f32", C.F32, C.FLAG_MASS_FIX)):
+        s = Solver(w["nx"], w["ny"], w["mobility"], w["width"], w["cfl"], recon=C.UPWIND5,
+                   precision=prec, vel_kind=w["vel_kind"], vel_param=w["vel_param"],
+                   flags=flags).init(w["phi0"])
+        rows = s.tune()
+        wall, ev_ms = time_steps(s, steps, warmup)
+        k_ms = time_kernel_only(s, min(steps, 50))
+        esize = 8 if prec == C.F64 else 4
+        achieved = WORDS_PER_LU * esize * lus / (k_ms * 1e-3) / 1e9
+        out[name] = {"value": round(lus * steps / (ev_ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+                     "ms_per_step": round(ev_ms / steps, 4), "kernel_ms": round(k_ms, 4),
+                     "achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "tile_rows": rows, "bytes_per_lu": WORDS_PER_LU * esize}
+        del s
+        torch.cuda.empty_cache()
+    return dict(out["f64"], dtype="f64", kernel="step_kernel, upwind-5 (wide patch)",
+                fp32=dict(out["f32"], dtype="f32", mass_correction="fused, every step"))
 
 
 def bench_shard_share(w, steps, warmup):
@@ -487,6 +516,8 @@ def main():
                         "tile_rows": f["tile_rows"], "tile_source": f["tile_source"]}
     if not args.no_t3s3 and not args.only:
         line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows_t3s3)
+    if not args.no_t2s5 and not args.only:
+        line["t2s5"] = bench_t2s5(w, args.steps, args.warmup)
     if not args.no_shard and not args.only:
         line["shard_share"] = bench_shard_share(w, args.steps, args.warmup)
     if not args.no_batch and not args.only:

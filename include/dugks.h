@@ -41,9 +41,8 @@
  *    per-step sum of plans with DUGKS_FLAG_MASS_FIX -- and DUGKS_ENUMERIC from
  *    then on.  Launches are asynchronous, so the status is read back with
  *    dugks_state_status (dugks_batch_status for the slots of a batch).
- *  - Reading of Eq. (2) where grad(phi) vanishes: n = g / sqrt(|g|^2 + 1e-8),
- *    g the isotropic gradient -- n = g/|g| to within (1e-4/|g|)^2 / 2 on an
- *    interface, continuous where g passes through 0.
+ *  - Reading of Eq. (2) where grad(phi) vanishes: n = g / max(|g|, 1e-12), g
+ *    the isotropic gradient.
  */
 #ifndef DUGKS_H
 #define DUGKS_H
@@ -75,8 +74,23 @@ typedef enum { DUGKS_F64 = 0, DUGKS_F32 = 1 } dugks_precision;
  *            and Hessian; mean of the two sides when xi_i is parallel to the
  *            face.                                                (T2S3)
  *  CENTRAL4  Eq. (25) with fourth-order central estimates of the face value
- *            and of both gradient components. */
-typedef enum { DUGKS_CENTRAL2 = 0, DUGKS_UPWIND3 = 1, DUGKS_CENTRAL4 = 2 } dugks_recon;
+ *            and of both gradient components.
+ *  UPWIND5   the fifth-order, non-isotropic reconstruction of DUGKS-T2S5
+ *            (Sec. III names it, gives no stencil): fbar+ at the foot
+ *            x_b - xi_i h by a tensor product of one-dimensional Lagrange
+ *            interpolations through the cell centres -- along the face
+ *            normal the five cells centred on the upstream cell (the six
+ *            centred on the face when xi_i is parallel to it), along the
+ *            tangent the five cells centred on the face's row (one when
+ *            xi_i is normal to the face).  T2 plans of the analytic velocity
+ *            kinds only (T3S3 or ARRAYS: DUGKS_EUNSUPPORTED); single grids
+ *            (batches refuse it). */
+typedef enum {
+  DUGKS_CENTRAL2 = 0,
+  DUGKS_UPWIND3 = 1,
+  DUGKS_CENTRAL4 = 2,
+  DUGKS_UPWIND5 = 3
+} dugks_recon;
 
 /* Prescribed velocity u(x, y, t); cell centres at (i + 1/2, j + 1/2):
  *  UNIFORM        u = p0, v = p1
@@ -321,6 +335,7 @@ int dugks_batch_set_tile_rows(dugks_batch *batch, int32_t rows);
  * Errors: EINVAL, EDEVICE. */
 int dugks_batch_tune(dugks_batch *batch, int32_t reps, int32_t *rows_out,
                      void *stream);
+
 
 const char *dugks_strerror(int status);
 

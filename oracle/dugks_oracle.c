@@ -45,17 +45,19 @@ static const double WQ[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
                              1.0 / 9.0,  1.0 / 36.0, 1.0 / 9.0,
                              1.0 / 36.0, 1.0 / 9.0,  1.0 / 36.0};
 static const double RT = 1.0 / 3.0;
-/* Eq. (2) is singular where grad(phi) vanishes (at the extrema of the small
- * over- and undershoots the schemes produce, where theta is not zero).
- * Reading: |grad(phi)| in the denominator of n is regularised,
- *   n = g / sqrt(|g|^2 + NORMAL_EPS^2),
- * which is g/|g| to within (NORMAL_EPS/|g|)^2/2 wherever an interface is
- * resolved, and a continuous function of g (slope <= 1/NORMAL_EPS) through
- * g = 0, so that rounding moves the source term by rounding-sized amounts. */
-static const double NORMAL_EPS = 1e-4;
+/* Eq. (2) is singular where grad(phi) vanishes.  Reading: n = g / |g| with
+ * |g| floored at NORMAL_EPS (n = 0 where phi is exactly flat).  Where g passes
+ * through zero while theta does not -- at the extrema of the small over- and
+ * undershoots the schemes produce -- n follows the rounding of g, and two
+ * roundings of the same arithmetic part from there on; smooth
+ * regularisations of |g| remove that but move the paper's own numbers (the
+ * T2S3 entries at C = 0.25 of Tables II, III, VIII, IX by up to 10 %), so
+ * the plain quotient is kept. */
+static const double NORMAL_EPS = 1e-12;
 
 static double normal_denominator(double gx, double gy) {
-  return sqrt(gx * gx + gy * gy + NORMAL_EPS * NORMAL_EPS);
+  const double g = sqrt(gx * gx + gy * gy);
+  return g > NORMAL_EPS ? g : NORMAL_EPS;
 }
 
 /* Grids below this many cells run their loops on one thread: the fork / join
@@ -485,10 +487,10 @@ static void step_ws(const oracle_params *p, long n, const double *tf,
       size_t c = IDX(nx, x, y);
       double gx, gy;
       normal_grad_at(nx, ny, phi, x, y, &gx, &gy);
+      theta[c] = theta_of(phi[c], p->width);
       double d = normal_denominator(gx, gy);
       nvx[c] = gx / d;
       nvy[c] = gy / d;
-      theta[c] = theta_of(phi[c], p->width);
     }
 
   /* 3. d(phi u)/dt at cell centres: backward difference over the last step,
@@ -597,6 +599,7 @@ static void cell_terms(const oracle_params *p, const double *phi, double t,
       size_t c = IDX(nx, x, y);
       double gx, gy;
       normal_grad_at(nx, ny, phi, x, y, &gx, &gy);
+      double th = theta_of(phi[c], p->width);
       double d = normal_denominator(gx, gy);
       double u, v, jx = 0.0, jy = 0.0, fe[9], sr[9];
       cell_velocity(p, x, y, t, &u, &v);
@@ -606,8 +609,7 @@ static void cell_terms(const oracle_params *p, const double *phi, double t,
         jx = (phi[c] * u - phi_ref[c] * u0) / (t - t_ref);
         jy = (phi[c] * v - phi_ref[c] * v0) / (t - t_ref);
       }
-      oracle_feq_source(phi[c], u, v, theta_of(phi[c], p->width), gx / d, gy / d, jx,
-                        jy, fe, sr);
+      oracle_feq_source(phi[c], u, v, th, gx / d, gy / d, jx, jy, fe, sr);
       for (int i = 0; i < 9; i++) {
         feq[i * N + c] = fe[i];
         src[i * N + c] = sr[i];
@@ -736,8 +738,8 @@ int oracle_init(const oracle_params *p, const double *phi0, double *tf,
       size_t c = IDX(nx, x, y);
       double gx, gy;
       normal_grad_at(nx, ny, phi0, x, y, &gx, &gy);
-      double d = normal_denominator(gx, gy);
       double theta = theta_of(phi0[c], p->width);
+      double d = normal_denominator(gx, gy);
       double u, v, fe[9], sr[9];
       cell_velocity(p, x, y, 0.0, &u, &v);
       oracle_feq_source(phi0[c], u, v, theta, gx / d, gy / d, 0.0, 0.0, fe, sr);

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "dugks.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = range(6)
 F64, F32 = 0, 1
-CENTRAL2, UPWIND3, CENTRAL4 = 0, 1, 2
+CENTRAL2, UPWIND3, CENTRAL4, UPWIND5 = 0, 1, 2, 3
 VEL_UNIFORM, VEL_ROTATION, VEL_SINGLE_VORTEX, VEL_DEFORMATION, VEL_ARRAYS = range(5)
 T2, T3S3 = 0, 1
 FLAG_DTPHIU_ZERO = 1

@@ -23,10 +23,19 @@ bool finite(double v) { return isfinite(v); }
 
 // ------------------------------------------------------------ stencils
 // bf = sum over the patch of c * fbar+, for face orientation o and velocity i.
-void add_tap(double (&c)[NTAP], int o, int s, int q, double v) {
+void add_tap(int recon, double (&c)[NTAP], int o, int s, int q, double v) {
   int dx = o == 0 ? s : q;
   int dy = o == 0 ? q : s;
-  c[tap_index(o, dx, dy)] += v;
+  c[tap_index(recon, o, dx, dy)] += v;
+}
+
+// Lagrange weight of node j among the unit-spaced nodes m0..m1 for the value
+// at coordinate x
+double lagrange_weight(int m0, int m1, int j, double x) {
+  double w = 1.0;
+  for (int k = m0; k <= m1; k++)
+    if (k != j) w *= (x - k) / (double)(j - k);
+  return w;
 }
 
 void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
@@ -37,7 +46,19 @@ void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
       // velocity components along the face normal (n) and tangent (t)
       const int en = o == 0 ? ex(i) : ey(i);
       const int et = o == 0 ? ey(i) : ex(i);
-      if (recon == DUGKS_UPWIND3) {
+      auto add = [&](int s, int q, double v) { add_tap(recon, c, o, s, q, v); };
+      if (recon == DUGKS_UPWIND5) {
+        // fbar+ at the foot x_b - xi h: along the normal at 1/2 - en h from
+        // the centre of L, through the five cells centred on the upstream
+        // cell (six centred on the face when en = 0); along the tangent at
+        // -et h, through five cells (one when et = 0)
+        const int n0 = en < 0 ? -1 : -2, n1 = en > 0 ? 2 : 3;
+        const int t0 = et != 0 ? -2 : 0, t1 = et != 0 ? 2 : 0;
+        for (int sn = n0; sn <= n1; sn++)
+          for (int q = t0; q <= t1; q++)
+            add(sn, q, lagrange_weight(n0, n1, sn, 0.5 - en * h) *
+                           lagrange_weight(t0, t1, q, -et * h));
+      } else if (recon == DUGKS_UPWIND3) {
         // foot of the characteristic relative to the centre of L, (n, t)
         const double pn = 0.5 - en * h, pt = -et * h;
         auto side = [&](int ks, double wgt) {
@@ -45,14 +66,14 @@ void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
           // H = 9 sum w_m (e_m e_m - I/3) f_m over the 3x3 patch about k
           const double dn = pn - ks, dq = pt;
           const double d2 = dn * dn + dq * dq;
-          add_tap(c, o, ks, 0, wgt);
+          add(ks, 0, wgt);
           for (int m = 0; m < 9; m++) {
             // the lattice is symmetric under x <-> y, so e_m in (n, t) axes
             const int mn = o == 0 ? ex(m) : ey(m);
             const int mt = o == 0 ? ey(m) : ex(m);
             const double de = dn * mn + dq * mt;
             const double v = 3.0 * wq(m) * de + 4.5 * wq(m) * (de * de - d2 / 3.0);
-            add_tap(c, o, ks + mn, mt, wgt * v);
+            add(ks + mn, mt, wgt * v);
           }
         };
         if (en > 0)
@@ -66,15 +87,15 @@ void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
       } else if (recon == DUGKS_CENTRAL2) {
         // F = (fL + fR)/2, dn = fR - fL, dt = (fL+t + fR+t - fL-t - fR-t)/4,
         // bf = F - h (en dn + et dt)
-        add_tap(c, o, 0, 0, 0.5);
-        add_tap(c, o, 1, 0, 0.5);
-        add_tap(c, o, 1, 0, -h * en);
-        add_tap(c, o, 0, 0, h * en);
+        add(0, 0, 0.5);
+        add(1, 0, 0.5);
+        add(1, 0, -h * en);
+        add(0, 0, h * en);
         const double q = -h * et * 0.25;
-        add_tap(c, o, 0, 1, q);
-        add_tap(c, o, 1, 1, q);
-        add_tap(c, o, 0, -1, -q);
-        add_tap(c, o, 1, -1, -q);
+        add(0, 1, q);
+        add(1, 1, q);
+        add(0, -1, -q);
+        add(1, -1, -q);
       } else {
         // fourth order on LL, L, R, RR (s = -1..2):
         // F = (-1, 9, 9, -1)/16, dn = (1, -27, 27, -1)/24,
@@ -83,11 +104,11 @@ void make_coefficients(int recon, double h, double (&coef)[2][9][NTAP]) {
         const double wN[4] = {1.0 / 24, -27.0 / 24, 27.0 / 24, -1.0 / 24};
         const double wD[5] = {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12};
         for (int s = -1; s <= 2; s++) {
-          add_tap(c, o, s, 0, wF[s + 1]);
-          add_tap(c, o, s, 0, -h * en * wN[s + 1]);
+          add(s, 0, wF[s + 1]);
+          add(s, 0, -h * en * wN[s + 1]);
           if (et != 0)
             for (int q = -2; q <= 2; q++)
-              if (q != 0) add_tap(c, o, s, q, -h * et * wF[s + 1] * wD[q + 2]);
+              if (q != 0) add(s, q, -h * et * wF[s + 1] * wD[q + 2]);
         }
       }
     }
@@ -101,17 +122,18 @@ bool make_compact(int recon, const double (&coef)[2][9][NTAP], double (&cp)[NCOM
   for (int k = 0; k < NCOMPACT; k++) cp[k] = 0.0;
   const int rep[4] = {0, 3, 1, 2};   // class 2|en|+|et| -> velocity (|en|, |et|)
   for (int c = 0; c < 4; c++)
-    for (int t = 0; t < NTAP; t++)
-      if (tap_used(recon, 0, rep[c], t)) cp[compact_index(0, rep[c], t)] = coef[0][rep[c]][t];
+    for (int t = 0; t < ntap(recon); t++)
+      if (tap_used(recon, 0, rep[c], t))
+        cp[compact_index(recon, 0, rep[c], t)] = coef[0][rep[c]][t];
   for (int o = 0; o < 2; o++)
     for (int i = 0; i < 9; i++)
-      for (int t = 0; t < NTAP; t++) {
+      for (int t = 0; t < ntap(recon); t++) {
         const double want = coef[o][i][t];
         if (!tap_used(recon, o, i, t)) {
           if (want != 0.0) return false;
           continue;
         }
-        const double got = cp[compact_index(o, i, t)];
+        const double got = cp[compact_index(recon, o, i, t)];
         if (fabs(got - want) > 1e-14 * (1.0 + fabs(want))) return false;
       }
   return true;
@@ -181,7 +203,7 @@ int validate(const dugks_params* p) {
   if (!finite(p->mobility) || !(p->mobility > 0.0)) return DUGKS_EINVAL;
   if (isnan(p->width) || !(p->width > 0.0)) return DUGKS_EINVAL;
   if (!finite(p->cfl) || !(p->cfl > 0.0) || p->cfl > 1.0) return DUGKS_EINVAL;
-  if (p->recon < 0 || p->recon > 2) return DUGKS_EINVAL;
+  if (p->recon < 0 || p->recon > 3) return DUGKS_EINVAL;
   if (p->precision < 0 || p->precision > 1) return DUGKS_EINVAL;
   if (p->vel_kind < 0 || p->vel_kind > 4) return DUGKS_EINVAL;
   if (p->flags & ~(DUGKS_FLAG_DTPHIU_ZERO | DUGKS_FLAG_MASS_FIX)) return DUGKS_EINVAL;
@@ -194,6 +216,11 @@ int validate(const dugks_params* p) {
   if ((p->vel_kind == DUGKS_VEL_SINGLE_VORTEX || p->vel_kind == DUGKS_VEL_DEFORMATION) &&
       !(p->vel_param[1] > 0.0))
     return DUGKS_EINVAL;
+  // the fifth-order reconstruction (DUGKS-T2S5) runs with the T2 time scheme
+  // and the analytic velocity kinds only
+  if (p->recon == DUGKS_UPWIND5 &&
+      (p->scheme != DUGKS_T2 || p->vel_kind == DUGKS_VEL_ARRAYS))
+    return DUGKS_EUNSUPPORTED;
   return DUGKS_OK;
 }
 
@@ -255,8 +282,11 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s, boo
     case DUGKS_UPWIND3:
       if (varr) DUGKS_LAUNCH(DUGKS_UPWIND3, true); else DUGKS_LAUNCH(DUGKS_UPWIND3, false);
       break;
-    default:
+    case DUGKS_CENTRAL4:
       if (varr) DUGKS_LAUNCH(DUGKS_CENTRAL4, true); else DUGKS_LAUNCH(DUGKS_CENTRAL4, false);
+      break;
+    default:   // upwind-5: T2, analytic velocities (validate)
+      if constexpr (STAGE == STAGE_T2) DUGKS_LAUNCH(DUGKS_UPWIND5, false);
       break;
   }
 #undef DUGKS_LAUNCH

@@ -317,8 +317,9 @@ int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint3
   if (!out) return DUGKS_EINVAL;
   *out = nullptr;
   if (capacity < 1 || capacity > 65536 || precision < 0 || precision > 1 || recon < 0 ||
-      recon > 2 || (flags & ~(DUGKS_FLAG_MASS_FIX | DUGKS_BATCH_T3S3)))
+      recon > 3 || (flags & ~(DUGKS_FLAG_MASS_FIX | DUGKS_BATCH_T3S3)))
     return DUGKS_EINVAL;
+  if (recon == DUGKS_UPWIND5) return DUGKS_EUNSUPPORTED;   // single grids only
   dugks_batch* B = new (std::nothrow) dugks_batch();
   if (!B) return DUGKS_ENOMEM;
   B->cap = capacity;

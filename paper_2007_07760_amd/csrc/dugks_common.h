@@ -26,23 +26,42 @@ __host__ __device__ constexpr double wq(int i) {
 // ------------------------------------------------------ stencil geometry
 // Face reconstruction bf_i = sum_t c[o][i][t] * fbar+_i(L + (dx_t, dy_t)),
 // with L the cell on the low side of the face.  o = 0: east face of L (normal
-// +x); o = 1: north face of L (normal +y).  Patch of offsets per orientation:
-//   o = 0: dx in [-1, 2], dy in [-2, 2]      o = 1: dx in [-2, 2], dy in [-1, 2]
-constexpr int NTAP = 20;
-__host__ __device__ constexpr int tap_dx(int o, int t) { return o == 0 ? (t % 4) - 1 : (t % 5) - 2; }
-__host__ __device__ constexpr int tap_dy(int o, int t) { return o == 0 ? (t / 4) - 2 : (t / 5) - 1; }
-__host__ __device__ constexpr int tap_index(int o, int dx, int dy) {
-  return o == 0 ? (dy + 2) * 4 + (dx + 1) : (dy + 1) * 5 + (dx + 2);
+// +x); o = 1: north face of L (normal +y).  s = offset along the face normal,
+// q = offset along the tangent, both from L.  Patch of offsets:
+//   central-2, upwind-3, central-4 (narrow): s in [-1, 2], q in [-2, 2]
+//     o = 0: dx in [-1, 2], dy in [-2, 2]    o = 1: dx in [-2, 2], dy in [-1, 2]
+//   upwind-5 (wide):                         s in [-2, 3], q in [-2, 2]
+//     o = 0: dx in [-2, 3], dy in [-2, 2]    o = 1: dx in [-2, 2], dy in [-2, 3]
+constexpr int NTAP = 30;   // the most taps of any patch (arrays are sized for it)
+__host__ __device__ constexpr bool wide(int recon) { return recon == DUGKS_UPWIND5; }
+__host__ __device__ constexpr int ntap(int recon) { return wide(recon) ? 30 : 20; }
+__host__ __device__ constexpr int tap_dx(int recon, int o, int t) {
+  return wide(recon) ? (o == 0 ? (t % 6) - 2 : (t % 5) - 2)
+                     : (o == 0 ? (t % 4) - 1 : (t % 5) - 2);
+}
+__host__ __device__ constexpr int tap_dy(int recon, int o, int t) {
+  return wide(recon) ? (o == 0 ? (t / 6) - 2 : (t / 5) - 2)
+                     : (o == 0 ? (t / 4) - 2 : (t / 5) - 1);
+}
+__host__ __device__ constexpr int tap_index(int recon, int o, int dx, int dy) {
+  return wide(recon) ? (o == 0 ? (dy + 2) * 6 + (dx + 2) : (dy + 2) * 5 + (dx + 2))
+                     : (o == 0 ? (dy + 2) * 4 + (dx + 1) : (dy + 1) * 5 + (dx + 2));
 }
 
-// Which taps a reconstruction uses (compile-time in the kernels).  s = offset
-// along the face normal, t = offset along the tangent, both from L.
+// Which taps a reconstruction uses (compile-time in the kernels).
 __host__ __device__ constexpr bool tap_used(int recon, int o, int i, int t) {
-  int dx = tap_dx(o, t), dy = tap_dy(o, t);
+  int dx = tap_dx(recon, o, t), dy = tap_dy(recon, o, t);
   int s = o == 0 ? dx : dy;
   int q = o == 0 ? dy : dx;
   int en = o == 0 ? ex(i) : ey(i);
   int et = o == 0 ? ey(i) : ex(i);
+  if (recon == DUGKS_UPWIND5) {
+    // five cells centred on the upstream cell along the normal (six centred on
+    // the face when en = 0), five along the tangent (one when et = 0)
+    int lo = en < 0 ? -1 : -2;
+    int hi = en > 0 ? 2 : 3;
+    return s >= lo && s <= hi && (et != 0 || q == 0);
+  }
   if (recon == DUGKS_UPWIND3) {
     int lo = en < 0 ? 0 : -1;   // upstream cell L (s=0) or R (s=1), 3x3 about it
     int hi = en > 0 ? 1 : 2;
@@ -66,9 +85,11 @@ __host__ __device__ constexpr bool tap_used(int recon, int o, int i, int t) {
 // exact symmetries of every scheme here, so no entry changes sign.
 //
 // Compact layout: class c = 2|en| + |et|, entry (s', q') at
-//   cbase(c) + (s' + 1) * 5 + (q' + 2),   s' in [-1, 2], q' in [-2, 2].
-constexpr int CCLASS = 20;            // entries per class
-constexpr int NCOMPACT = 4 * CCLASS;  // 80 slots, at most ~48 used
+//   c * cclass + (s' - smin) * 5 + (q' + 2),   q' in [-2, 2],
+// s' in [-1, 2] (narrow patch, smin = -1, cclass = 20) or [-2, 3] (wide,
+// smin = -2, cclass = 30).
+constexpr int NCOMPACT = 4 * 30;  // slots for the widest patch
+__host__ __device__ constexpr int cclass(int recon) { return wide(recon) ? 30 : 20; }
 __host__ __device__ constexpr int cls_of(int en, int et) {
   return 2 * (en < 0 ? -en : en) + (et < 0 ? -et : et);
 }
@@ -79,13 +100,14 @@ __host__ __device__ constexpr int canon_q(int et, int q) {
   return et < 0 ? -q : (et == 0 ? (q < 0 ? -q : q) : q);
 }
 // compact index of tap t of (o, i)
-__host__ __device__ constexpr int compact_index(int o, int i, int t) {
-  int dx = tap_dx(o, t), dy = tap_dy(o, t);
+__host__ __device__ constexpr int compact_index(int recon, int o, int i, int t) {
+  int dx = tap_dx(recon, o, t), dy = tap_dy(recon, o, t);
   int s = o == 0 ? dx : dy;
   int q = o == 0 ? dy : dx;
   int en = o == 0 ? ex(i) : ey(i);
   int et = o == 0 ? ey(i) : ex(i);
-  return cls_of(en, et) * CCLASS + (canon_s(en, s) + 1) * 5 + (canon_q(et, q) + 2);
+  return cls_of(en, et) * cclass(recon) + (canon_s(en, s) + (wide(recon) ? 2 : 1)) * 5 +
+         (canon_q(et, q) + 2);
 }
 
 // ------------------------------------------------------------- march tiles
@@ -94,16 +116,21 @@ __host__ __device__ constexpr int compact_index(int o, int i, int t) {
 constexpr int LANES = 64;
 constexpr int HALO = 3;
 constexpr int OWN = LANES - 2 * HALO;
-constexpr int LPAD = 2;                 // LDS row padding each side
-constexpr int LROW = LANES + 2 * LPAD;  // LDS row length (elements)
+// LDS row padding each side (the taps reach 2 columns past a lane, 3 for the
+// wide patch) and LDS row length, in elements
+__host__ __device__ constexpr int lpad(int recon) { return wide(recon) ? 3 : 2; }
+__host__ __device__ constexpr int lrow(int recon) { return LANES + 2 * lpad(recon); }
 
 
 // Wavefronts per SIMD the step kernels are built for (the register budget of
 // each variant: 512 / waves VGPRs), and so resident per CU (x 4 SIMDs).  The
 // FP32 variants with the fused mass correction or the 5-row ring of central-4
 // need more than 128 registers: 3.
+// Upwind-5 (wide patch, 6-row ring, the edge lanes' extra column): 1 (FP64,
+// whose ring lets at most 5 wavefronts share a CU's LDS anyway) and 2 (FP32).
 __host__ __device__ constexpr int step_waves(int esize, int recon, bool mfix) {
-  return esize == 8 ? 2 : ((recon == DUGKS_CENTRAL4 || mfix) ? 3 : 4);
+  return wide(recon) ? (esize == 8 ? 1 : 2)
+                     : (esize == 8 ? 2 : ((recon == DUGKS_CENTRAL4 || mfix) ? 3 : 4));
 }
 
 // ------------------------------------------------------------- state layout
@@ -150,13 +177,9 @@ constexpr int MASS_GROUP = 8;
 constexpr double MASS_FIT_MAX = 1e-3;
 constexpr int FIX_THREADS = 1024;   // threads of the block that reduces the groups
 
-// The unit normal of Eq. (2) is read as n = g / sqrt(|g|^2 + NORMAL_EPS^2), g
-// the isotropic gradient of phi: n = g/|g| to within (NORMAL_EPS/|g|)^2/2 on
-// every interface, and a continuous function of g with a slope bounded by
-// 1/NORMAL_EPS where the gradient vanishes (at the extrema of the scheme's
-// small over- and undershoots), so that rounding at such a point moves the
-// source term by rounding-sized amounts rather than by flipping n.
-constexpr double NORMAL_EPS = 1e-4;
+// The unit normal of Eq. (2): n = g / max(|g|, NORMAL_EPS), g the isotropic
+// gradient of phi (n = 0 where phi is exactly flat).
+constexpr double NORMAL_EPS = 1e-12;
 
 struct Layout {
   size_t esize;        // bytes per element (8 or 4)

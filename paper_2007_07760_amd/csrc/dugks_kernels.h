@@ -97,6 +97,7 @@ template <typename T>
 struct RowRegs {
   T f[9];
   T hp;
+  T g[9];     // wide patch, lanes 0 and 63: f~ of the column beyond the halo
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) {
@@ -177,21 +178,29 @@ __device__ __forceinline__ void collision_target(T pC, T mx, T my, T (&x)[9]) {
   x[4] = P2 + dmp; x[8] = P2 - dmp;
 }
 
-// num / sqrt(|g|^2 + NORMAL_EPS^2) (the regularised |g| of the normal), the
-// square root and the quotient rounded exactly (a hardware reciprocal square
-// root in FP32 was ~1 % faster, but moved the FP32 field of the 64^2
-// translation by 5x more in L-inf)
+// theta / max(|g|, NORMAL_EPS), the square root and the quotient rounded
+// exactly (a hardware reciprocal square root in FP32 was ~1 % faster, but
+// moved the FP32 field of the 64^2 translation by 5x more in L-inf)
 template <typename T>
-__device__ __forceinline__ T over_norm(T num, T gx, T gy) {
-  const T e2 = T(NORMAL_EPS * NORMAL_EPS);
-  return num / sqrt(fma(gx, gx, fma(gy, gy, e2)));
+__device__ __forceinline__ T over_norm(T theta, T gx, T gy) {
+  const T gm = sqrt(fma(gx, gx, gy * gy));
+  return theta / (gm > T(NORMAL_EPS) ? gm : T(NORMAL_EPS));
 }
 
 // VARR: the velocity comes from caller-supplied cell arrays (steady; a face
 // takes the mean of its two cells) instead of the separable tables.
 template <typename T, int R, bool MFIX, int STAGE = STAGE_T2, bool VARR = false>
 struct Marcher {
-  static constexpr int RB = (R == DUGKS_CENTRAL4) ? 5 : 4;
+  // the wide (upwind-5) patch reaches 2 rows below and 3 above the face row
+  // and 3 columns beyond a lane: a 6-row ring, faces 3 rows behind the cell
+  // terms, and lanes 0 / 63 compute phi of the column beyond them as well
+  // (so that fbar+ is right on every lane); the narrow patches: a 4-row ring
+  // (5 for central-4), faces 2 rows behind
+  static constexpr bool WIDE = wide(R);
+  static constexpr int RB = WIDE ? 6 : ((R == DUGKS_CENTRAL4) ? 5 : 4);
+  static constexpr int LAG = WIDE ? 3 : 2;
+  static constexpr int LP = lpad(R);
+  static constexpr int LR = lrow(R);
   // the fused mass correction: the stored state's loads take the pending
   // correction (T2; T3S3 stage A, which reads f^^n), the state's writes give
   // the new mass partials (T2; stage B, which writes f^^{n+1})
@@ -204,7 +213,7 @@ struct Marcher {
   const T* __restrict__ tabx;
   cptr<T> taby;
   const T* __restrict__ uv;   // VARR: u plane then v plane, [ny][nx]
-  T (*bfp)[9][LROW];   // [RB][9][LROW] ring of fbar+ rows
+  T (*bfp)[9][LR];     // [RB][9][LR] ring of fbar+ rows
   int lane, col;
   int ocol;                 // owned lanes: column within the strip
   // the strip's own chunk column of the output (rdst), of stage A's second
@@ -212,16 +221,17 @@ struct Marcher {
   // (rin: stage B reads phi^n there); the strip's mass partials
   rsrc_t rdst, rdst2, rpart, raux, rin;
   int64_t loff;             // chunk offset of the lane's column (strip, x % OWN)
+  int64_t loffx;            // wide patch, lanes 0 / 63: that of the column beyond
   bool owned;
   int y0, y1, base;
   T UXc, VXc, UXe, VXe;
   T gN, gP, gH, jscale;
-  // own-column pipeline (registers)
-  T ph0, ph1, ph2, ph3;     // phi of rows r-2 .. r+1
+  // own-column pipeline (registers; index 0 is the face row k = r - LAG)
+  T ph[LAG + 2];            // phi of rows r-LAG .. r+1
   T D0, D1, D2;             // phi(x+1) - phi(x-1) of rows r-1 .. r+1
   T A0, A1, A2;             // phi(x-1) + 4 phi(x) + phi(x+1) of rows r-1 .. r+1
-  T sx0, sy0, sx1, sy1, sx2, sy2;  // s = theta n + J/RT of rows r-2 .. r
-  T cp0, cp1, cp2, cx0, cx1, cx2, cy0, cy1, cy2;  // phi, m of rows r-2 .. r
+  T sxp[LAG + 1], syp[LAG + 1];   // s = theta n + J/RT of rows r-LAG .. r
+  T cp[LAG + 1], cx[LAG + 1], cy[LAG + 1];   // phi, m of rows r-LAG .. r
   T fS[9];                  // dt*alpha*fbar of the face below (north face of k-1)
   T PS, QSx, QSy;           // its collision part, see face_stage
   // mass correction (MFIX): the stored f~_i of the cells whose stored f~_0 is
@@ -251,7 +261,8 @@ struct Marcher {
   }
 
   __device__ __forceinline__ void load_row(RowRegs<T>& d, int row) {
-    const T* p = row_src(wrapi(row, a.ny));
+    const int rw = wrapi(row, a.ny);
+    const T* p = row_src(rw);
 #pragma unroll
     for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
     if (FIX_LOAD) {
@@ -260,6 +271,16 @@ struct Marcher {
       for (int i = 0; i < 9; i++) d.f[i] = fit ? d.f[i] + cw(i) : d.f[i];
     }
     d.hp = p[9 * OWN];
+    if (WIDE && (lane == 0 || lane == LANES - 1)) {
+      const T* q = src + (int64_t)rw * a.CH + loffx;
+#pragma unroll
+      for (int i = 0; i < 9; i++) d.g[i] = q[i * OWN];
+      if (FIX_LOAD) {
+        const bool fit = d.g[0] < fitmax;
+#pragma unroll
+        for (int i = 0; i < 9; i++) d.g[i] = fit ? d.g[i] + cw(i) : d.g[i];
+      }
+    }
   }
 
   // phi = sum_i f~_i (Eq. 30, pairwise) of a new row and its horizontal
@@ -267,8 +288,17 @@ struct Marcher {
   __device__ __forceinline__ void phi_push(const RowRegs<T>& d) {
     const T p = (((d.f[0] + d.f[1]) + (d.f[2] + d.f[3])) +
                  ((d.f[4] + d.f[5]) + (d.f[6] + d.f[7]))) + d.f[8];
-    const T pE = from_right(p), pW = from_left(p);
-    ph0 = ph1; ph1 = ph2; ph2 = ph3; ph3 = p;
+    T pE = from_right(p), pW = from_left(p);
+    if (WIDE) {
+      // the edge lanes' outer neighbour: the column they loaded besides their own
+      const T px = (((d.g[0] + d.g[1]) + (d.g[2] + d.g[3])) +
+                    ((d.g[4] + d.g[5]) + (d.g[6] + d.g[7]))) + d.g[8];
+      pW = lane == 0 ? px : pW;
+      pE = lane == LANES - 1 ? px : pE;
+    }
+#pragma unroll
+    for (int j = 0; j < LAG + 1; j++) ph[j] = ph[j + 1];
+    ph[LAG + 1] = p;
     D0 = D1; D1 = D2; D2 = pE - pW;
     A0 = A1; A1 = A2; A2 = fma(T(4), p, pW + pE);
   }
@@ -276,12 +306,12 @@ struct Marcher {
   // cell-centred terms of row r: isotropic normal, theta (Eqs. 2, 4),
   // d(phi u)/dt, feq and S (Eq. 14) collapsed into fbar+ (Eq. 23) -> LDS ring
   __device__ __forceinline__ void cell_stage(const RowRegs<T>& d, int r) {
-    const int L = LPAD + lane;
+    const int L = LP + lane;
     const T twelfth = T(1) / T(12);
     // (1/RT) sum_k w_k e_k phi_k, column-summed
     const T gx = fma(T(4), D1, D0 + D2) * twelfth;
     const T gy = (A2 - A0) * twelfth;
-    const T pC = ph2;
+    const T pC = ph[LAG];
     const T th = over_norm(a.kth * pC * (T(1) - pC), gx, gy);   // theta / |grad phi|
     const int rr = wrapi(r, a.ny);
     T Uc, Vc;                                      // spatial part of u
@@ -295,18 +325,32 @@ struct Marcher {
     const T dj = fma(gN, pC, -(gP * d.hp)) * jscale;   // d(phi g)/dt
     const T sx = fma(th, gx, T(3) * (Uc * dj));        // s = theta n + J / RT
     const T sy = fma(th, gy, T(3) * (Vc * dj));
-    sx0 = sx1; sy0 = sy1; sx1 = sx2; sy1 = sy2; sx2 = sx; sy2 = sy;
     const T mx = fma(a.tau, sx, T(3) * pC * (gN * Uc));
     const T my = fma(a.tau, sy, T(3) * pC * (gN * Vc));
-    cp0 = cp1; cp1 = cp2; cp2 = pC;
-    cx0 = cx1; cx1 = cx2; cx2 = mx;
-    cy0 = cy1; cy1 = cy2; cy2 = my;
+#pragma unroll
+    for (int j = 0; j < LAG; j++) {
+      sxp[j] = sxp[j + 1]; syp[j] = syp[j + 1];
+      cp[j] = cp[j + 1]; cx[j] = cx[j + 1]; cy[j] = cy[j + 1];
+    }
+    sxp[LAG] = sx; syp[LAG] = sy;
+    cp[LAG] = pC; cx[LAG] = mx; cy[LAG] = my;
     T x[9];
     collision_target(pC, mx, my, x);
-    // fbar+ in increment form: its moments follow those of X exactly
+    // fbar+ in increment form, fbar+_i = f~_i + cB2 (X_i - f~_i): its moments
+    // follow those of X.  The increments sum to zero (sum_i X_i = phi =
+    // sum_i f~_i), which the rest direction enforces in the arithmetic of the
+    // others: the rounding of phi itself then moves no mass.  (Near phi = 1
+    // every cell rounds phi alike, and the plain increments made FP32 gain
+    // ~3e-9 of the total mass per step.)
     T* bf = &bfp[slotB(r)][0][0];
+    T dsum = T(0);
 #pragma unroll
-    for (int i = 0; i < 9; i++) bf[i * LROW + L] = fma(a.cB2, x[i] - d.f[i], d.f[i]);
+    for (int i = 1; i < 9; i++) {
+      const T dx = x[i] - d.f[i];
+      dsum += dx;
+      bf[i * LR + L] = fma(a.cB2, dx, d.f[i]);
+    }
+    bf[L] = fma(a.cB2, -dsum, d.f[0]);
   }
 
   // one face value: fixed stencil over the fbar+ ring (Eqs. 24-26); the
@@ -314,13 +358,13 @@ struct Marcher {
   // registers), the tap pattern is compile-time
   template <int O>
   __device__ __forceinline__ T recon(int i, int k) const {
-    const int L = LPAD + lane;
+    const int L = LP + lane;
     T v = T(0);
 #pragma unroll
-    for (int t = 0; t < NTAP; t++) {
+    for (int t = 0; t < ntap(R); t++) {
       if (tap_used(R, O, i, t)) {
-        const T f = bfp[slotB(k + tap_dy(O, t))][i][L + tap_dx(O, t)];
-        v = fma(cf[compact_index(O, i, t)], f, v);
+        const T f = bfp[slotB(k + tap_dy(R, O, t))][i][L + tap_dx(R, O, t)];
+        v = fma(cf[compact_index(R, O, i, t)], f, v);
       }
     }
     return v;
@@ -333,7 +377,7 @@ struct Marcher {
   // a collision part in the 3 numbers (P, Qx, Qy) of each face.
   template <bool upd>
   __device__ __forceinline__ void face_stage(int k) {
-    const int L = LPAD + lane;
+    const int L = LP + lane;
     const int kk = wrapi(k, a.ny);
     // stage B: Q of the row (Eq. 32 value) and phi^n, the history plane of
     // stage A's f~(t') (the input), read before the face work so that the
@@ -388,8 +432,8 @@ struct Marcher {
     // phN = dt*alpha*phi_b; P = beta phi_b, Q = 3 P u_b + gamma s_b, all
     // carried pre-multiplied by dt so that dt f_b,i = pn_i + w_i (P + e_i.Q)
     const T PN = a.pscale * phN;
-    const T QNx = fma(T(3) * PN, ubN, a.gdt * (sx0 + sx1));
-    const T QNy = fma(T(3) * PN, vbN, a.gdt * (sy0 + sy1));
+    const T QNx = fma(T(3) * PN, ubN, a.gdt * (sxp[0] + sxp[1]));
+    const T QNy = fma(T(3) * PN, vbN, a.gdt * (syp[0] + syp[1]));
     const T dP = PN - PS, dQx = QNx - QSx, dQy = QNy - QSy;
     PS = PN; QSx = QNx; QSy = QNy;
     if (!upd) return;
@@ -408,8 +452,8 @@ struct Marcher {
     const T ubE = VARR ? T(0.5) * (uk + from_right(uk)) : gH * (UXe * UY[2 * kk + 1]);
     const T vbE = VARR ? T(0.5) * (vk + from_right(vk)) : gH * (VXe * VY[2 * kk + 1]);
     const T PE = a.pscale * phE;
-    const T QEx = fma(T(3) * PE, ubE, a.gdt * (sx0 + from_right(sx0)));
-    const T QEy = fma(T(3) * PE, vbE, a.gdt * (sy0 + from_right(sy0)));
+    const T QEx = fma(T(3) * PE, ubE, a.gdt * (sxp[0] + from_right(sxp[0])));
+    const T QEy = fma(T(3) * PE, vbE, a.gdt * (syp[0] + from_right(syp[0])));
     const T eP = PE - from_left(PE), eQx = QEx - from_left(QEx), eQy = QEy - from_left(QEy);
     {
       // i = 1, 5 (axis) and 2, 4, 6, 8 (diagonal)
@@ -430,16 +474,27 @@ struct Marcher {
     double cs = 0.0, cf0 = 0.0;
     {
       T x[9];
-      collision_target(cp0, cx0, cy0, x);
+      collision_target(cp[0], cx[0], cy[0], x);
       // the new row is not read again by this launch: stream it past the
       // caches; lanes outside the owned columns store nothing
       const unsigned ob = owned ? (unsigned)((kk * a.CH + ocol) * (int)sizeof(T)) : OFF_NONE;
       constexpr unsigned PL = OWN * sizeof(T);
+      // X - fbar+ with a zero sum enforced in the rest direction (see
+      // cell_stage), plane 0 last
+      T dsum = T(0);
       if (STAGE == STAGE_T2) {
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
+        for (int j = 0; j < 9; j++) {
+          const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          const T tfp = fma(a.kap, x[i] - bp, bp);
+          T dx;
+          if (i != 0) {
+            dx = x[i] - bp;
+            dsum += dx;
+          } else {
+            dx = -dsum;
+          }
+          const T tfp = fma(a.kap, dx, bp);
           const T v = tfp + out[i];
           bstore(v, rdst, ob + i * PL);
           if (FIX_SUM) {
@@ -447,25 +502,40 @@ struct Marcher {
             if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
           }
         }
-        bstore(ph0, rdst, ob + 9 * PL);
+        bstore(ph[0], rdst, ob + 9 * PL);
       } else if (STAGE == STAGE_A) {
         // f~(t') = f~+ + (1/3) dt L* and Q = f^n + (3/7) dt L*, with
         // f~+ = fbar+ + kap (X - fbar+) and f^n = fbar+ - kap (X - fbar+)
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
+        for (int j = 0; j < 9; j++) {
+          const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          const T d = x[i] - bp;
+          T d;
+          if (i != 0) {
+            d = x[i] - bp;
+            dsum += d;
+          } else {
+            d = -dsum;
+          }
           bstore(fma(a.wo1, out[i], fma(a.kap, d, bp)), rdst, ob + i * PL);
           bstore(fma(a.wo2, out[i], fma(-a.kap, d, bp)), rdst2, ob + i * PL);
         }
-        bstore(ph0, rdst, ob + 9 * PL);   // Q needs no history plane: stage B reads this one
+        bstore(ph[0], rdst, ob + 9 * PL);   // Q needs no history plane: stage B reads this one
       } else {
         // f^^{n+1} = Q + kap (X' - fbar+) + (4/7) dt L**, kap (X' - fbar+)
         // being (3/4) dt (Omega + S) at t'; phi^n goes on as the history
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
+        for (int j = 0; j < 9; j++) {
+          const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          const T v = fma(a.wo1, out[i], fma(a.kap, x[i] - bp, qv[i]));
+          T dx;
+          if (i != 0) {
+            dx = x[i] - bp;
+            dsum += dx;
+          } else {
+            dx = -dsum;
+          }
+          const T v = fma(a.wo1, out[i], fma(a.kap, dx, qv[i]));
           bstore(v, rdst, ob + i * PL);
           if (FIX_SUM) {
             cs += owned ? (double)v : 0.0;
@@ -502,49 +572,58 @@ struct Marcher {
   }
 
   // row r of the march: phi of r+1, cell terms of r, load r+2 (the last rows
-  // load row y1 + 2 again, so that every row issues the same loads), faces
-  // of r-2 (none for the first rows of the tile; the north faces only for
+  // load row y1 + LAG again, so that every row issues the same loads), faces
+  // of r-LAG (none for the first rows of the tile; the north faces only for
   // row y0 - 1, the south faces of row y0)
   template <int FACE>
   __device__ __forceinline__ void body(int r, RowRegs<T>& cur, RowRegs<T>& nxt) {
     phi_push(nxt);
     cell_stage(cur, r);
-    load_row(cur, min(r + 2, y1 + 2));
+    load_row(cur, min(r + 2, y1 + LAG));
     wave_sync();
-    if (FACE == 1) face_stage<false>(r - 2);
-    if (FACE == 2) face_stage<true>(r - 2);
+    if (FACE == 1) face_stage<false>(r - LAG);
+    if (FACE == 2) face_stage<true>(r - LAG);
     wave_sync();
   }
 
   __device__ void run() {
     RowRegs<T> B, C;
     macc = mcnt = 0.0;
-    cp0 = cp1 = cp2 = cx0 = cx1 = cx2 = cy0 = cy1 = cy2 = T(0);
-    ph0 = ph1 = ph2 = ph3 = T(0);
+#pragma unroll
+    for (int j = 0; j < LAG + 1; j++) sxp[j] = syp[j] = cp[j] = cx[j] = cy[j] = T(0);
+#pragma unroll
+    for (int j = 0; j < LAG + 2; j++) ph[j] = T(0);
     D0 = D1 = D2 = A0 = A1 = A2 = T(0);
-    sx0 = sy0 = sx1 = sy1 = sx2 = sy2 = T(0);
     PS = QSx = QSy = T(0);
 #pragma unroll
     for (int i = 0; i < 9; i++) fS[i] = T(0);
-    load_row(C, y0 - 3);
+#pragma unroll
+    for (int i = 0; i < 9; i++) B.g[i] = C.g[i] = T(0);
+    // cell terms from row y0 - LAG (the lowest row the faces of row y0 - 1
+    // reach), their phi from row y0 - LAG - 1
+    load_row(C, y0 - LAG - 1);
     phi_push(C);
-    load_row(B, y0 - 2);
+    load_row(B, y0 - LAG);
     phi_push(B);
-    load_row(C, y0 - 1);
-    body<0>(y0 - 2, B, C);
-    body<0>(y0 - 1, C, B);
-    body<0>(y0, B, C);
-    body<1>(y0 + 1, C, B);
+    load_row(C, y0 - LAG + 1);
+#pragma unroll
+    for (int j = 0; j < 2 * LAG - 1; j++) {
+      if (j & 1)
+        body<0>(y0 - LAG + j, C, B);
+      else
+        body<0>(y0 - LAG + j, B, C);
+    }
+    body<1>(y0 + LAG - 1, C, B);
     // the first full row before the loop, so that the loop is entered, as it
     // is repeated, right after a full row's loads and stores: the waits for
     // the loads at its head then never include stores
-    body<2>(y0 + 2, B, C);
-    int r = y0 + 3;
-    for (; r + 1 <= y1 + 1; r += 2) {
+    body<2>(y0 + LAG, B, C);
+    int r = y0 + LAG + 1;
+    for (; r + 1 <= y1 + LAG - 1; r += 2) {
       body<2>(r, C, B);
       body<2>(r + 1, B, C);
     }
-    if (r <= y1 + 1) body<2>(r, C, B);
+    if (r <= y1 + LAG - 1) body<2>(r, C, B);
   }
 };
 
@@ -561,9 +640,9 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
                                            const T* __restrict__ uv,
                                            double* __restrict__ part, double pend,
                                            double fitmax, int strip,
-                                           int seg, T (*s_bfp)[9][LROW]) {
-  Marcher<T, R, MFIX, STAGE, VARR> m{a, src, as_const(cf), tabx, as_const(taby), uv,
-                                     s_bfp};
+                                           int seg, T (*s_bfp)[9][lrow(R)]) {
+  using M = Marcher<T, R, MFIX, STAGE, VARR>;
+  M m{a, src, as_const(cf), tabx, as_const(taby), uv, s_bfp};
   const int lane = threadIdx.x;
   const int x0 = strip * OWN;
   m.lane = lane;
@@ -572,6 +651,14 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   {
     const int cs = m.col / OWN;
     m.loff = (int64_t)cs * a.ny * a.CH + (m.col - cs * OWN);
+  }
+  m.loffx = m.loff;
+  if (M::WIDE && (lane == 0 || lane == LANES - 1)) {
+    // the column beyond the lane, outwards (wrapped)
+    int cx = lane == 0 ? m.col - 1 : m.col + 1;
+    cx = cx < 0 ? cx + a.nx : (cx >= a.nx ? cx - a.nx : cx);
+    const int cs = cx / OWN;
+    m.loffx = (int64_t)cs * a.ny * a.CH + (cx - cs * OWN);
   }
   const int nown = min(OWN, a.nx - x0);
   m.owned = lane >= HALO && lane < HALO + nown;
@@ -587,7 +674,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<T>& a, int64_t n,
   }
   m.y0 = seg * a.seg_rows;
   m.y1 = min(m.y0 + a.seg_rows, a.ny);
-  m.base = m.y0 - 3;
+  m.base = m.y0 - M::LAG - 1;   // at or below every ring row the tile touches
   if (!VARR) {
     const int ce = m.col + 1;  // east face of the column (x + 1), unwrapped
     m.UXc = tabx[2 * m.col + 1];
@@ -628,7 +715,8 @@ step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__
             const T* __restrict__ uv, double* __restrict__ part,
             const StateHeader* __restrict__ hdr) {
   constexpr int RB = Marcher<T, R, MFIX, STAGE, VARR>::RB;
-  __shared__ T s_bfp[RB][9][LROW];
+  constexpr int LR = lrow(R);
+  __shared__ T s_bfp[RB][9][LR];
 
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
   // each XCD a contiguous band of tiles (shared halos stay in one L2)
@@ -639,7 +727,7 @@ step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__
   const int seg = logical / a.nstrips;
 
   // the LDS pads are never read into owned results; keep them finite
-  for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
+  for (int j = threadIdx.x; j < RB * 9 * LR; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
   __syncthreads();
   const double pend = MFIX ? hdr->pending : 0.0;
   const double fitmax = MFIX ? hdr->fit_max : 0.0;
@@ -815,8 +903,9 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
     const GridDesc<T>* __restrict__ desc, const SlotStep* __restrict__ steps,
     const BatchCtl* __restrict__ ctl, unsigned* __restrict__ head) {
   constexpr int RB = Marcher<T, R, MFIX, STAGE>::RB;
-  __shared__ T s_bfp[RB][9][LROW];
-  for (int j = threadIdx.x; j < RB * 9 * LROW; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
+  constexpr int LR = lrow(R);
+  __shared__ T s_bfp[RB][9][LR];
+  for (int j = threadIdx.x; j < RB * 9 * LR; j += LANES) (&s_bfp[0][0][0])[j] = T(0);
   __syncthreads();
   // descriptors, counters and the work list are not written while the kernel
   // runs: uniform reads through the scalar cache
@@ -919,7 +1008,8 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs<T> a) {
                     ((P(1, 1) - P(-1, 1)) + (P(1, -1) - P(-1, -1))) / 12.0;
   const double gy = (P(0, 1) - P(0, -1)) / 3.0 +
                     ((P(1, 1) - P(1, -1)) + (P(-1, 1) - P(-1, -1))) / 12.0;
-  const double den = sqrt(gx * gx + gy * gy + NORMAL_EPS * NORMAL_EPS);
+  const double gm = sqrt(gx * gx + gy * gy);
+  const double den = gm > NORMAL_EPS ? gm : NORMAL_EPS;
   const double th = a.kth * pC * (1.0 - pC);
   const double nvx = gx / den, nvy = gy / den;
   double u, v;

@@ -42,7 +42,7 @@ def _p(**kw):
     return C.make_params(flags=flags, tile_rows=tile, scheme=scheme, **base)
 
 
-@pytest.mark.parametrize("recon", [C.CENTRAL2, C.UPWIND3, C.CENTRAL4])
+@pytest.mark.parametrize("recon", [C.CENTRAL2, C.UPWIND3, C.CENTRAL4, C.UPWIND5])
 @pytest.mark.parametrize("prec", [C.F64, C.F32])
 def test_plan_create_valid(lib, recon, prec):
     # plan creation also checks that the stencil table folds onto its compact
@@ -64,13 +64,26 @@ def test_plan_create_valid(lib, recon, prec):
     (dict(mobility=0.0), C.EINVAL), (dict(mobility=-1.0), C.EINVAL),
     (dict(mobility=math.inf), C.EINVAL), (dict(width=0.0), C.EINVAL),
     (dict(width=math.nan), C.EINVAL), (dict(cfl=0.0), C.EINVAL), (dict(cfl=1.01), C.EINVAL),
-    (dict(recon=3), C.EINVAL), (dict(precision=2), C.EINVAL), (dict(vel_kind=5), C.EINVAL),
+    (dict(recon=4), C.EINVAL), (dict(precision=2), C.EINVAL), (dict(vel_kind=5), C.EINVAL),
     (dict(vel_param=(math.nan, 0.0)), C.EINVAL), (dict(flags=4), C.EINVAL),
     (dict(tile_rows=-1), C.EINVAL),
     (dict(vel_kind=C.VEL_SINGLE_VORTEX, vel_param=(0.05, 0.0)), C.EINVAL),
 ])
 def test_plan_create_rejects(lib, bad, code):
     assert C.dugks_plan_create_status(_p(**bad)) == code
+
+
+def test_upwind5_only_where_provided(lib):
+    """The fifth-order reconstruction: T2 plans of the analytic kinds; the
+    T3S3 time scheme, velocity arrays and batches refuse it as unsupported."""
+    assert C.dugks_plan_create_status(_p(recon=C.UPWIND5)) == C.OK
+    assert C.dugks_plan_create_status(
+        _p(recon=C.UPWIND5, scheme=C.T3S3, mobility=0.05)) == C.EUNSUPPORTED
+    assert C.dugks_plan_create_status(
+        _p(recon=C.UPWIND5, vel_kind=C.VEL_ARRAYS)) == C.EUNSUPPORTED
+    out = __import__("ctypes").c_void_p()
+    assert lib.dugks_batch_create(4, 0, C.UPWIND5, 0,
+                                  __import__("ctypes").byref(out)) == C.EUNSUPPORTED
 
 
 def test_velocity_arrays_plan(lib):

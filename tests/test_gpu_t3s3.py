@@ -39,7 +39,7 @@ def test_t3s3_ragged_all_schemes(gpu, orc, recon, kind):
     for steps in (1, 2, 23):
         g.step(steps)
         o.run(steps)
-        _check(g, o, f"t3s3 ragged +{steps}")
+        _check(g, o, f"t3s3 ragged +{steps}", orc)
     checkpoints_run(g, orc, o.p, (400, 1500), "t3s3 ragged")
 
 
@@ -52,7 +52,7 @@ def test_t3s3_slotted_disk_checkpoints(gpu, orc):
                  w["vel_kind"], w["vel_param"], w["phi0"], scheme=1)
     g.step(200)
     o.run(200)
-    _check(g, o, "t3s3 c2 step 200")
+    _check(g, o, "t3s3 c2 step 200", orc)
     checkpoints_run(g, orc, o.p, (1000, 2000, 3000, 4000, 5000, 6000, 7000, 7999),
                     "t3s3 c2")
 
@@ -66,7 +66,7 @@ def test_t3s3_edge_sizes(gpu, orc, shape, tile):
                      tile_rows=tile, scheme=1)
         g.step(10)
         o.run(10)
-        _check(g, o, f"t3s3 edge recon {recon}")
+        _check(g, o, f"t3s3 edge recon {recon}", orc)
 
 
 def test_t3s3_tile_shape_invariance_bitwise(gpu):
@@ -188,4 +188,4 @@ def test_t3s3_headline_size_two_steps(gpu, orc):
         if o is None:
             o = o2.run(2)
         g.step(2)
-        _check(g, o, f"t3s3 h1 step 2 tile {tile}")
+        _check(g, o, f"t3s3 h1 step 2 tile {tile}")   # o is shared by the tile heights
