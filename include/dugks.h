@@ -336,6 +336,37 @@ int dugks_batch_set_tile_rows(dugks_batch *batch, int32_t rows);
 int dugks_batch_tune(dugks_batch *batch, int32_t reps, int32_t *rows_out,
                      void *stream);
 
+/* ------------------------------------------------- allocation-free variant
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * dugks_step_many_noalloc is the batch step (dugks_batch_step) of many
+ * independent grids without a batch: grid j (plans[j], states[j], initialised
+ * by dugks_init, currently at step steps[j]) advances by nsteps steps, each
+ * step one persistent launch of the batch step kernel over every grid's tiles
+ * (two for T3S3) and the finish kernel; results are bitwise those of
+ * dugks_step and of a batch.  Nothing is allocated: descriptors, step
+ * counters, slot status and the work list live in one fixed 1 MiB device
+ * array of the library per GPU, filled by small set-up kernels whose inputs
+ * travel as kernel arguments; no hipMalloc, hipFree, pinned staging or graph.
+ *  - plans, states, steps: host arrays of n entries.  Every plan of one
+ *    precision, reconstruction, DUGKS_FLAG_MASS_FIX setting and time scheme;
+ *    each grid is tiled at its own plan's tile height.
+ *  - Limits: 1 <= n <= 256 grids and at most 116288 tiles (strips x row
+ *    segments) over all grids; beyond them DUGKS_EINVAL, before anything is
+ *    launched.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents (each call rewrites what it reads first).  Calls that
+ *    overlap on one GPU -- other streams, other threads -- race: the caller
+ *    orders them.
+ *  - The step counters stay the caller's: grid j ends at steps[j] + nsteps,
+ *    unless its state turns non-finite (status DUGKS_ENUMERIC, see
+ *    dugks_state_status), which stops it early.
+ * Asynchronous on `stream`.  Errors: EINVAL (NULL arrays, a NULL or
+ * misaligned state, mixed plans, the limits), EUNSUPPORTED (ARRAYS velocity or
+ * the upwind-5 reconstruction, which the batch kernels do not provide),
+ * EDEVICE. */
+int dugks_step_many_noalloc(const dugks_plan *const *plans, void *const *states,
+                            const int64_t *steps, int32_t n, int64_t nsteps, void *stream);
 
 const char *dugks_strerror(int status);
 

@@ -65,6 +65,7 @@ def load() -> ctypes.CDLL:
     L.dugks_history.argtypes = [vp, vp, i64, vp, vp]
     L.dugks_state_status.argtypes = [vp, vp, vp, vp]
     L.dugks_batch_status.argtypes = [vp, vp, vp]
+    L.dugks_step_many_noalloc.argtypes = [vp, vp, vp, i32, i64, vp]
     L.dugks_step.argtypes = [vp, vp, i64, i64, vp]
     L.dugks_phi.argtypes = [vp, vp, i64, vp, vp]
     L.dugks_mass.argtypes = [vp, vp, i64, vp, vp]
@@ -88,6 +89,7 @@ def load() -> ctypes.CDLL:
     L.dugks_tune.argtypes = [P, vp, i64, i32, ctypes.POINTER(i32), vp]
     for name in ("dugks_plan_create", "dugks_init", "dugks_step", "dugks_phi",
                  "dugks_distributions", "dugks_history", "dugks_state_status", "dugks_batch_status",
+                 "dugks_step_many_noalloc",
                  "dugks_mass", "dugks_mass_correct", "dugks_mass0",
                  "dugks_batch_create", "dugks_batch_set", "dugks_batch_clear",
                  "dugks_batch_commit", "dugks_batch_step", "dugks_batch_steps",
@@ -179,6 +181,17 @@ def dugks_state_status(plan: int, state: int, out: int, stream: int) -> None:
 
 def dugks_batch_status(batch: int, out: int, stream: int) -> None:
     _check(load().dugks_batch_status(batch, out, stream), "dugks_batch_status")
+
+
+def dugks_step_many_noalloc(plans, states, steps, nsteps: int, stream: int) -> None:
+    """plans, states, steps: sequences of n entries (plan handles, state device
+    addresses, current steps)."""
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*plans)
+    S = (ctypes.c_void_p * n)(*states)
+    N = (ctypes.c_int64 * n)(*steps)
+    _check(load().dugks_step_many_noalloc(P, S, N, n, nsteps, stream),
+           "dugks_step_many_noalloc")
 
 
 def dugks_mass(plan: int, state: int, step: int, out_dev: int, stream: int) -> None:
