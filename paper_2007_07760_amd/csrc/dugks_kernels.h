@@ -201,6 +201,10 @@ struct Marcher {
   static constexpr int LAG = WIDE ? 3 : 2;
   static constexpr int LP = lpad(R);
   static constexpr int LR = lrow(R);
+  // FP32: the relaxation increments X_i - g_i are made to sum to zero in the
+  // rest direction (see cell_stage); FP64 rounds phi to 1e-16 and keeps the
+  // plain increments, as the oracle writes them
+  static constexpr bool ZSUM = sizeof(T) == 4;
   // the fused mass correction: the stored state's loads take the pending
   // correction (T2; T3S3 stage A, which reads f^^n), the state's writes give
   // the new mass partials (T2; stage B, which writes f^^{n+1})
@@ -338,19 +342,19 @@ struct Marcher {
     collision_target(pC, mx, my, x);
     // fbar+ in increment form, fbar+_i = f~_i + cB2 (X_i - f~_i): its moments
     // follow those of X.  The increments sum to zero (sum_i X_i = phi =
-    // sum_i f~_i), which the rest direction enforces in the arithmetic of the
-    // others: the rounding of phi itself then moves no mass.  (Near phi = 1
-    // every cell rounds phi alike, and the plain increments made FP32 gain
-    // ~3e-9 of the total mass per step.)
+    // sum_i f~_i); in FP32 the rest direction enforces that in the arithmetic
+    // of the others, so that the rounding of phi itself moves no mass (near
+    // phi = 1 every cell rounds phi alike, and the plain increments made FP32
+    // gain ~3e-9 of the total mass per step)
     T* bf = &bfp[slotB(r)][0][0];
     T dsum = T(0);
 #pragma unroll
     for (int i = 1; i < 9; i++) {
       const T dx = x[i] - d.f[i];
-      dsum += dx;
+      if (ZSUM) dsum += dx;
       bf[i * LR + L] = fma(a.cB2, dx, d.f[i]);
     }
-    bf[L] = fma(a.cB2, -dsum, d.f[0]);
+    bf[L] = fma(a.cB2, ZSUM ? -dsum : x[0] - d.f[0], d.f[0]);
   }
 
   // one face value: fixed stencil over the fbar+ ring (Eqs. 24-26); the
@@ -479,7 +483,7 @@ struct Marcher {
       // caches; lanes outside the owned columns store nothing
       const unsigned ob = owned ? (unsigned)((kk * a.CH + ocol) * (int)sizeof(T)) : OFF_NONE;
       constexpr unsigned PL = OWN * sizeof(T);
-      // X - fbar+ with a zero sum enforced in the rest direction (see
+      // X - fbar+ (FP32: with a zero sum enforced in the rest direction, see
       // cell_stage), plane 0 last
       T dsum = T(0);
       if (STAGE == STAGE_T2) {
@@ -487,12 +491,9 @@ struct Marcher {
         for (int j = 0; j < 9; j++) {
           const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          T dx;
-          if (i != 0) {
-            dx = x[i] - bp;
-            dsum += dx;
-          } else {
-            dx = -dsum;
+          T dx = x[i] - bp;
+          if (ZSUM) {
+            if (i != 0) dsum += dx; else dx = -dsum;
           }
           const T tfp = fma(a.kap, dx, bp);
           const T v = tfp + out[i];
@@ -510,12 +511,9 @@ struct Marcher {
         for (int j = 0; j < 9; j++) {
           const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          T d;
-          if (i != 0) {
-            d = x[i] - bp;
-            dsum += d;
-          } else {
-            d = -dsum;
+          T d = x[i] - bp;
+          if (ZSUM) {
+            if (i != 0) dsum += d; else d = -dsum;
           }
           bstore(fma(a.wo1, out[i], fma(a.kap, d, bp)), rdst, ob + i * PL);
           bstore(fma(a.wo2, out[i], fma(-a.kap, d, bp)), rdst2, ob + i * PL);
@@ -528,12 +526,9 @@ struct Marcher {
         for (int j = 0; j < 9; j++) {
           const int i = j < 8 ? j + 1 : 0;
           const T bp = bfp[slotB(k)][i][L];
-          T dx;
-          if (i != 0) {
-            dx = x[i] - bp;
-            dsum += dx;
-          } else {
-            dx = -dsum;
+          T dx = x[i] - bp;
+          if (ZSUM) {
+            if (i != 0) dsum += dx; else dx = -dsum;
           }
           const T v = fma(a.wo1, out[i], fma(a.kap, dx, qv[i]));
           bstore(v, rdst, ob + i * PL);
