@@ -48,6 +48,11 @@ CPU_STEPS = 16         # oracle sample of the headline grid: about 10-20 s on th
 CLOCK_WARMUP_STEPS = 50
 
 
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -470,6 +475,7 @@ def main():
             phi=s.phi().double().cpu().numpy(), mass0=s.mass0(), mass=s.mass())
         del s
         torch.cuda.empty_cache()
+        progress(f"{prec_name} {results[prec_name]['mlups']:.0f} MLUPS")
     copy_gbs = copy_bandwidth()
     head = "f64" if "f64" in results else "f32"
     r = results[head]
@@ -525,16 +531,22 @@ def main():
                         "tile_rows": f["tile_rows"], "tile_source": f["tile_source"]}
     if not args.no_t3s3 and not args.only:
         line["t3s3"] = bench_t3s3(w, args.steps, args.warmup, args.tile_rows_t3s3)
+        progress("t3s3 done")
     if not args.no_t2s5 and not args.only:
         line["t2s5"] = bench_t2s5(w, args.steps, args.warmup)
+        progress("t2s5 done")
     if not args.no_shard and not args.only:
         line["shard_share"] = bench_shard_share(w, args.steps, args.warmup)
+        progress("shard_share done")
     if not args.no_batch and not args.only:
         line["batched"] = bench_batched(args.batch_steps)
+        progress("batched done")
     if not args.no_serve and not args.only:
         line["serving"] = bench_serving(args.serve_requests)
+        progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
+        progress("cpu_baseline done")
     print(json.dumps(line), flush=True)
 
 
