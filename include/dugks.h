@@ -259,7 +259,8 @@ int dugks_mass0(const dugks_plan *plan, const void *state, double *out_dev,
  * need them: a batch has `capacity` slots, each holding a (plan, state) pair
  * of the batch's precision and reconstruction, the step the state is at and
  * the step to stop at.  One persistent kernel takes the tiles of every active
- * grid from a work list in device memory (taller tiles first) -- for
+ * grid from a work list in device memory, cut into one queue per XCD (whole
+ * small grids or bands of a large one, taller tiles first) -- for
  * DUGKS_BATCH_T3S3 batches one such kernel per stage; a last, tiny kernel then
  * advances each active slot's step counter (and applies the fused mass
  * correction of DUGKS_FLAG_MASS_FIX batches).  Results are bitwise those of
@@ -351,7 +352,7 @@ int dugks_batch_tune(dugks_batch *batch, int32_t reps, int32_t *rows_out,
  *  - plans, states, steps: host arrays of n entries.  Every plan of one
  *    precision, reconstruction, DUGKS_FLAG_MASS_FIX setting and time scheme;
  *    each grid is tiled at its own plan's tile height.
- *  - Limits: 1 <= n <= 256 grids and at most 116288 tiles (strips x row
+ *  - Limits: 1 <= n <= 256 grids and at most 116192 tiles (strips x row
  *    segments) over all grids; beyond them DUGKS_EINVAL, before anything is
  *    launched.
  *  - Every call on one GPU shares that GPU's array, which keeps the last

@@ -127,6 +127,8 @@ struct dugks_batch {
   // host side
   std::vector<Slot> slots;
   std::vector<BatchItem> items;
+  std::vector<int32_t> qstart;        // queue q: items [qstart[q], qstart[q + 1])
+  int nq = 1;
   bool desc_dirty = true;
   int rows = DEFAULT_ROWS;            // tile height (rows per item)
   int grid_blocks = 0;                // resident wavefronts of the persistent kernel
@@ -149,18 +151,35 @@ GridDesc<T> make_desc(const Slot& s, int rows) {
   return make_grid_desc<T>(s.plan, s.state, rows);
 }
 
-// Work list for tile height `rows`: every tile of every attached slot, the
-// taller tiles first so that the short ones fill the tail of the step.
+// Work list for tile height `rows`, cut into NQUEUE queues of about equal
+// work (one per XCD).  The slots' tiles, largest slot first and each slot's
+// tiles segment by segment, are laid end to end and cut at equal shares of
+// the marched rows, so a queue holds whole small grids or a band of segments
+// of a large one: tiles that share halos stay in one XCD's L2.  Within a
+// queue the taller tiles come first, so that the short ones fill the tail.
 void build_items(dugks_batch* B, int rows) {
   B->items.clear();
   struct Keyed {
     int h;
     BatchItem it;
   };
-  std::vector<Keyed> v;
+  std::vector<std::pair<int64_t, int>> order;   // (marched rows, slot)
   for (int k = 0; k < B->cap; k++) {
     const Slot& s = B->slots[k];
     if (!s.plan) continue;
+    const int ny = s.plan->p.ny;
+    const int seg = std::min(rows, ny);
+    const int64_t nsegs = (ny + seg - 1) / seg;
+    order.push_back({(int64_t)s.plan->nstrips * (ny + 5 * nsegs), k});
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) {
+                     return a.first > b.first;
+                   });
+  std::vector<Keyed> v;
+  for (const auto& o : order) {
+    const int k = o.second;
+    const Slot& s = B->slots[k];
     const int ny = s.plan->p.ny, nstrips = s.plan->nstrips;
     const int seg = std::min(rows, ny);
     const int nsegs = (ny + seg - 1) / seg;
@@ -169,7 +188,22 @@ void build_items(dugks_batch* B, int rows) {
       for (int st = 0; st < nstrips; st++) v.push_back({h, {k, g * nstrips + st}});
     }
   }
-  std::stable_sort(v.begin(), v.end(), [](const Keyed& a, const Keyed& b) { return a.h > b.h; });
+  int64_t total = 0;
+  for (const Keyed& k : v) total += k.h + 5;
+  B->nq = v.empty() ? 1 : NQUEUE;
+  B->qstart.assign(NQUEUE + 1, (int32_t)v.size());
+  B->qstart[0] = 0;
+  size_t i = 0;
+  int64_t done = 0;
+  for (int q = 0; q < B->nq; q++) {
+    const size_t first = i;
+    // up to the queue's share of the work (the last queue takes the rest)
+    const int64_t upto = total * (q + 1) / B->nq;
+    while (i < v.size() && (q == B->nq - 1 || done + v[i].h + 5 <= upto)) done += v[i++].h + 5;
+    std::stable_sort(v.begin() + first, v.begin() + i,
+                     [](const Keyed& a, const Keyed& b) { return a.h > b.h; });
+    B->qstart[q + 1] = (int32_t)i;
+  }
   B->items.reserve(v.size());
   for (const Keyed& k : v) B->items.push_back(k.it);
 }
@@ -213,7 +247,9 @@ int upload(dugks_batch* B, hipStream_t s) {
   BatchCtl* ctl = reinterpret_cast<BatchCtl*>(h);
   ctl->items = B->d_items;
   ctl->nitems = (int32_t)B->items.size();
-  ctl->pad = 0;
+  ctl->nq = B->nq;
+  for (int q = 0; q <= NQUEUE; q++)
+    ctl->qstart[q] = q < (int)B->qstart.size() ? B->qstart[q] : ctl->nitems;
   hipError_t e;
   if ((e = hipMemcpyAsync(B->d_ctl, ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s)))
     return hip_status(e);
@@ -343,12 +379,12 @@ int dugks_batch_create(int32_t capacity, int32_t precision, int32_t recon, uint3
       hipMalloc(reinterpret_cast<void**>(&B->d_status), capacity * sizeof(int32_t)) !=
           hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&B->d_ctl), sizeof(BatchCtl)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&B->d_head), 256) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&B->d_head), HEAD_BYTES) != hipSuccess ||
       hipMemset(B->d_desc, 0, capacity * B->desc_bytes) != hipSuccess ||
       hipMemset(B->d_steps, 0, capacity * sizeof(SlotStep)) != hipSuccess ||
       hipMemset(B->d_status, 0, capacity * sizeof(int32_t)) != hipSuccess ||
       hipMemset(B->d_ctl, 0, sizeof(BatchCtl)) != hipSuccess ||
-      hipMemset(B->d_head, 0, 256) != hipSuccess ||
+      hipMemset(B->d_head, 0, HEAD_BYTES) != hipSuccess ||
       hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     release(B);
     delete B;
@@ -468,14 +504,14 @@ int dugks_batch_tune(dugks_batch* batch, int32_t reps, int32_t* rows_out, void* 
     // one untimed pass, then the timed passes
     if ((rc = batch_launch(batch, s, false))) break;
     // the step kernels alone leave the queue heads at their ends: rewind them
-    if (hipMemsetAsync(batch->d_head, 0, 2 * sizeof(unsigned), s) != hipSuccess) {
+    if (hipMemsetAsync(batch->d_head, 0, HEAD_BYTES, s) != hipSuccess) {
       rc = DUGKS_EDEVICE;
       break;
     }
     (void)hipEventRecord(e0, s);
     for (int r = 0; r < reps && rc == DUGKS_OK; r++) {
       rc = batch_launch(batch, s, false);
-      if (!rc && hipMemsetAsync(batch->d_head, 0, 2 * sizeof(unsigned), s) != hipSuccess)
+      if (!rc && hipMemsetAsync(batch->d_head, 0, HEAD_BYTES, s) != hipSuccess)
         rc = DUGKS_EDEVICE;
     }
     (void)hipEventRecord(e1, s);

@@ -885,10 +885,22 @@ struct BatchItem {
   int32_t slot, tile;
 };
 
+// The work list is cut into up to NQUEUE queues, one per XCD: consecutive
+// blocks of a launch go round-robin to the 8 XCDs, so block b drains queue
+// b % nq first, and the tiles that share halo rows and columns (one grid's
+// neighbouring strips and segments, kept together in one queue) meet in one
+// L2.  A block whose own queue is drained takes items from the others.
+constexpr int NQUEUE = 8;
+// Queue q keeps its heads (stage A or T2, then stage B) in a 128-byte line of
+// its own: atomics from different XCDs on one line run several times slower.
+constexpr int HEAD_STRIDE = 32;
+constexpr size_t HEAD_BYTES = NQUEUE * HEAD_STRIDE * sizeof(unsigned);
+
 struct BatchCtl {
   const BatchItem* items;
   int32_t nitems;
-  int32_t pad;
+  int32_t nq;                    // queues in use, 1..NQUEUE
+  int32_t qstart[NQUEUE + 1];    // queue q holds items [qstart[q], qstart[q + 1])
 };
 
 // One batch step (STAGE_T2), or one stage of a T3S3 batch step, over the work
@@ -906,38 +918,45 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
   // runs: uniform reads through the scalar cache
   const cptr<BatchCtl> c = as_const(ctl);
   const cptr<BatchItem> items = as_const(c->items);
-  const unsigned nitems = (unsigned)c->nitems;
   const cptr<SlotStep> st = as_const(steps);
-  unsigned* qhead = head + (STAGE == STAGE_B ? 1 : 0);
-  for (;;) {
-    unsigned it = 0;
-    if (threadIdx.x == 0) it = atomicAdd(qhead, 1u);
-    it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= nitems) break;
-    const BatchItem w = load_const(items + it);
-    const int64_t n = st[w.slot].n;
-    if (n >= st[w.slot].target) continue;
-    const cptr<GridDesc<T>> d = as_const(desc) + w.slot;
-    const StepArgs<T> a = load_const(as_const(STAGE == STAGE_B ? &d->b : &d->a));
-    const int strip = w.tile % a.nstrips;
-    const int seg = w.tile / a.nstrips;
-    const int b = (int)(n & 1);
-    const double pend = MFIX ? d->hdr->pending : 0.0;
-    const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
-    if (STAGE == STAGE_T2)
-      march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf,
-                                    d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
-                                    s_bfp);
-    else if (STAGE == STAGE_A)   // f^^n -> f~(t'), Q
-      march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->mid, d->q, nullptr, d->cf, d->tabx,
-                                    d->taby, nullptr, d->part, pend, fitmax, strip, seg, s_bfp);
-    else                         // f~(t'), Q -> f^^{n+1}
-      march_tile<T, R, MFIX, STAGE>(a, n, d->mid, d->buf[b ^ 1], nullptr, d->q, d->cf2,
-                                    d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
-                                    s_bfp);
-    // the next item's ring starts from its own rows; order this tile's LDS
-    // reads before them
-    wave_sync();
+  const int nq = c->nq;
+  const int home = nq > 0 ? (int)(blockIdx.x % (unsigned)nq) : 0;
+  unsigned* heads = head + (STAGE == STAGE_B ? 1 : 0);
+  for (int qi = 0; qi < nq; qi++) {
+    const int q = home + qi < nq ? home + qi : home + qi - nq;
+    const unsigned lo = (unsigned)c->qstart[q];
+    const unsigned cnt = (unsigned)c->qstart[q + 1] - lo;
+    unsigned* qh = heads + q * HEAD_STRIDE;
+    for (;;) {
+      unsigned it = 0;
+      if (threadIdx.x == 0) it = atomicAdd(qh, 1u);
+      it = __builtin_amdgcn_readfirstlane(it);
+      if (it >= cnt) break;
+      const BatchItem w = load_const(items + lo + it);
+      const int64_t n = st[w.slot].n;
+      if (n >= st[w.slot].target) continue;
+      const cptr<GridDesc<T>> d = as_const(desc) + w.slot;
+      const StepArgs<T> a = load_const(as_const(STAGE == STAGE_B ? &d->b : &d->a));
+      const int strip = w.tile % a.nstrips;
+      const int seg = w.tile / a.nstrips;
+      const int b = (int)(n & 1);
+      const double pend = MFIX ? d->hdr->pending : 0.0;
+      const double fitmax = MFIX ? d->hdr->fit_max : 0.0;
+      if (STAGE == STAGE_T2)
+        march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->buf[b ^ 1], nullptr, nullptr, d->cf,
+                                      d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
+                                      s_bfp);
+      else if (STAGE == STAGE_A)   // f^^n -> f~(t'), Q
+        march_tile<T, R, MFIX, STAGE>(a, n, d->buf[b], d->mid, d->q, nullptr, d->cf, d->tabx,
+                                      d->taby, nullptr, d->part, pend, fitmax, strip, seg, s_bfp);
+      else                         // f~(t'), Q -> f^^{n+1}
+        march_tile<T, R, MFIX, STAGE>(a, n, d->mid, d->buf[b ^ 1], nullptr, d->q, d->cf2,
+                                      d->tabx, d->taby, nullptr, d->part, pend, fitmax, strip, seg,
+                                      s_bfp);
+      // the next item's ring starts from its own rows; order this tile's LDS
+      // reads before them
+      wave_sync();
+    }
   }
 }
 
@@ -951,7 +970,8 @@ __global__ __launch_bounds__(FIX_THREADS) void batch_finish_kernel(
     const GridDesc<T>* __restrict__ desc, SlotStep* __restrict__ steps,
     unsigned* __restrict__ head, int32_t* __restrict__ status) {
   const int slot = blockIdx.x;
-  if (slot == 0 && threadIdx.x < 2) head[threadIdx.x] = 0u;   // both queue heads
+  if (slot == 0 && threadIdx.x < 2 * NQUEUE)   // every queue head, both stages
+    head[(threadIdx.x >> 1) * HEAD_STRIDE + (threadIdx.x & 1)] = 0u;
   const int64_t n = steps[slot].n;
   if (n >= steps[slot].target) return;
   const GridDesc<T>& d = desc[slot];

@@ -23,13 +23,15 @@ namespace {
 // (no host staging buffer, no allocation).  Layout of the array:
 constexpr int NOALLOC_GRIDS = 256;
 constexpr size_t NOALLOC_BYTES = size_t(1) << 20;
-constexpr size_t NA_CTL = 0, NA_HEAD = 256, NA_STEPS = 512;
+constexpr size_t NA_CTL = 0, NA_HEAD = 256, NA_STEPS = NA_HEAD + HEAD_BYTES;
 constexpr size_t NA_STATUS = NA_STEPS + NOALLOC_GRIDS * sizeof(SlotStep);
 constexpr size_t NA_DESC = (NA_STATUS + NOALLOC_GRIDS * sizeof(int32_t) + 255) / 256 * 256;
 constexpr size_t NA_ITEMS =
     (NA_DESC + NOALLOC_GRIDS * sizeof(GridDesc<double>) + 255) / 256 * 256;
 constexpr int64_t NOALLOC_ITEMS = (int64_t)((NOALLOC_BYTES - NA_ITEMS) / sizeof(BatchItem));
 static_assert(sizeof(GridDesc<double>) >= sizeof(GridDesc<float>), "descriptor sizes");
+static_assert(sizeof(BatchCtl) <= NA_HEAD - NA_CTL, "control block");
+static_assert(NA_STEPS % 256 == 0, "alignment");
 
 // descriptors of up to DESC_CHUNK grids, by value
 constexpr int DESC_CHUNK = 8;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(64) void noalloc_desc_kernel(DescChunk<T> c, unsign
 
 // the work list: item i belongs to the grid j with start[j] <= i < start[j+1]
 // (grids in decreasing order of tile height), tile i - start[j]; one thread
-// also writes the control block and rewinds both queue heads
+// also writes the control block and rewinds the queue heads
 struct ItemStarts {
   int32_t start[NOALLOC_GRIDS + 1];
   int32_t grid[NOALLOC_GRIDS];
@@ -72,10 +74,10 @@ static __global__ __launch_bounds__(256) void noalloc_items_kernel(ItemStarts a,
     BatchCtl* ctl = reinterpret_cast<BatchCtl*>(base + NA_CTL);
     ctl->items = items;
     ctl->nitems = nitems;
-    ctl->pad = 0;
+    ctl->nq = 1;   // one queue: the list is in order of tile height only
+    for (int q = 0; q <= NQUEUE; q++) ctl->qstart[q] = q == 0 ? 0 : nitems;
     unsigned* head = reinterpret_cast<unsigned*>(base + NA_HEAD);
-    head[0] = 0u;
-    head[1] = 0u;
+    for (int q = 0; q < NQUEUE; q++) head[q * HEAD_STRIDE] = head[q * HEAD_STRIDE + 1] = 0u;
   }
   if (i >= nitems) return;
   int lo = 0, hi = a.n - 1;   // last j with start[j] <= i
