@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-kernel-rows", type=int, default=0,
+                    help="only the batch kernel on the C4 grids at this tile height, "
+                         "--batch-steps plain launches (counter runs)")
     ap.add_argument("--only-batch", action="store_true",
                     help="the batched section alone (profiling runs)")
     ap.add_argument("--no-t3s3", action="store_true")
@@ -291,6 +294,34 @@ def bench_shard_share(w, steps, warmup):
             "ms_per_step": round(ev_ms / steps, 4), "dtype": "f64", "tile_rows": rows}
 
 
+def bench_batch_kernel(steps, rows):
+    """The batch kernel alone on the C4 grids (for counter runs): tile height
+    `rows`, `steps` plain launches (no autotuner, no graph, no one-grid path)."""
+    import torch
+    from paper_2007_07760_amd import _lib as C
+    from paper_2007_07760_amd import inputs as I
+    from paper_2007_07760_amd.batch import Batch
+    from paper_2007_07760_amd.solver import Solver
+    grids = I.batch_grids(256, seed=0)
+    b = Batch(len(grids), C.F32, C.UPWIND3, C.FLAG_MASS_FIX)
+    sol = [Solver(g["nx"], g["ny"], g["mobility"], g["width"], g["cfl"], recon=g["recon"],
+                  precision=C.F32, vel_kind=g["vel_kind"], vel_param=g["vel_param"],
+                  flags=C.FLAG_MASS_FIX).init(I.batch_phi0(g)) for g in grids]
+    for k, s in enumerate(sol):
+        b.set(k, s, s.step_index + steps)
+    b.tile_rows = rows
+    b.commit()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps, graph_steps=0)
+    e1.record()
+    torch.cuda.synchronize()
+    cells = sum(g["nx"] * g["ny"] for g in grids)
+    return {"workload": f"256 periodic grids (c4), {cells} cells, FP32 + fused mass correction",
+            "tile_rows": rows, "steps": steps,
+            "ms_per_step": round(e0.elapsed_time(e1) / steps, 4)}
+
+
 def bench_batched(steps):
     """C4: 256 independent grids, FP32 + fused mass correction, upwind-3.
     Batched: one persistent kernel per step over all grids, hipGraph replays
@@ -448,6 +479,11 @@ def main():
         w = dict(w, nx=n, ny=n, phi0=I.random_circles(n, n, 64, 20.0 * n / 4096,
                                                       200.0 * n / 4096, 4.0, 0))
     lus = w["nx"] * w["ny"]
+    if args.batch_kernel_rows:
+        print(json.dumps({"batch_kernel": bench_batch_kernel(args.batch_steps,
+                                                             args.batch_kernel_rows)}),
+              flush=True)
+        return
     if args.only_batch:
         print(json.dumps({"batched": bench_batched(args.batch_steps)}), flush=True)
         return
