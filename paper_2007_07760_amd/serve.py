@@ -162,6 +162,8 @@ class Server:
         keep = set(keep_phi)
         t_note = time.perf_counter()
         dev = self.device
+        self.budget_blocked_rounds = 0
+        self.slots_peak = 0
         too_big = [r["id"] for r in trace if state_bytes(r) > self.pool.nbytes - ALIGN]
         if too_big:
             raise ValueError(f"requests {too_big[:5]} do not fit in the HBM budget")
@@ -185,11 +187,13 @@ class Server:
                 # admission: arrival order, later requests may pass one that
                 # does not fit yet
                 k = 0
+                blocked = False
                 while k < len(queue) and free:
                     req = queue[k]
                     nb = sizes.get(req["id"]) or sizes.setdefault(req["id"], state_bytes(req))
                     off = self.pool.alloc(nb)
                     if off is None:
+                        blocked = True
                         k += 1
                         continue
                     queue.pop(k)
@@ -201,6 +205,9 @@ class Server:
                     changed = True
                 if changed:
                     self.batch.commit()
+                # rounds in which a free slot stayed empty for want of memory
+                self.budget_blocked_rounds += int(blocked and bool(free))
+                self.slots_peak = max(self.slots_peak, len(active))
                 if active:
                     j = rounds & 1
                     self.batch.step(self.K, graph_steps=self.K)
@@ -342,6 +349,8 @@ def main(argv=None) -> int:
         srv = Server(args.slots, int(args.budget_gb * (1 << 30)), args.graph_steps)
         res = srv.run(trace, keep_phi=sample, progress=note)
         extra = {"pool_peak_gb": round(srv.pool.peak / (1 << 30), 3), "slots": args.slots,
+                 "budget_gb": args.budget_gb, "slots_peak": srv.slots_peak,
+                 "budget_blocked_rounds": srv.budget_blocked_rounds,
                  "graph_steps": args.graph_steps, "tile_rows": srv.batch.tile_rows}
         del srv
     else:

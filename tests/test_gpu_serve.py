@@ -36,6 +36,9 @@ def test_serve_mix_equals_alone(serve):
     res = srv.run(trace, keep_phi=[r["id"] for r in trace])
     assert [r.id for r in res] == [r["id"] for r in trace]
     assert srv.pool.used == 0 and srv.pool.peak <= srv.pool.nbytes
+    assert 1 <= srv.slots_peak <= 5
+    print(f"pool peak {srv.pool.peak} B, slots peak {srv.slots_peak}, rounds with a free "
+          f"slot held back by the budget {srv.budget_blocked_rounds}", flush=True)
     for r, req in zip(res, trace):
         assert r.done >= r.admitted >= r.arrival - 1e-9
         ref = serve.run_alone(req)
