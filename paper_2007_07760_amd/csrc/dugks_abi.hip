@@ -268,7 +268,8 @@ int launch_stage(const dugks_plan* P, void* state, int64_t n, hipStream_t s, boo
   }
   double* part = at<double>(state, L.off_groups);
   StateHeader* hd = at<StateHeader>(state, 0);
-  const int per = (a.nlogical + 7) / 8;
+  // blocks per XCD (see step_kernel's tile order)
+  const int per = a.ileave > 1 ? a.ileave * a.clen * a.nstrips : (a.nlogical + 7) / 8;
   dim3 grid(per * 8), block(LANES);
   const bool varr = P->p.vel_kind == DUGKS_VEL_ARRAYS;
   const T* uv = varr ? at<T>(state, L.off_vel) : nullptr;

@@ -47,6 +47,8 @@ inline GridDesc<T> make_grid_desc(const dugks_plan* P, void* state, int rows) {
     a->seg_rows = seg;
     a->nsegs = (P->p.ny + seg - 1) / seg;
     a->nlogical = a->nstrips * a->nsegs;
+    a->ileave = 1;   // unused: a batch takes its tiles from its work queues
+    a->clen = a->nsegs;
   }
   if (t3) {
     d.mid = at<T>(state, L.off_mid);

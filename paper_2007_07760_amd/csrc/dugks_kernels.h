@@ -36,6 +36,7 @@ struct StepArgs {
   int64_t CH;            // strip-chunk length (elements), see Tiling
   int nx, ny;
   int seg_rows, nstrips, nsegs, nlogical;
+  int ileave, clen;      // tile order of step_kernel (see there)
   int ngroups;           // row groups of MASS_GROUP rows (mass partials)
   T cB2;                 // fbar+ = g + cB2 (feq + tau S - g), g the stage's input
   T kap;                 // output = base + kap (feq + tau S - fbar+) + wo1 dt L
@@ -714,12 +715,30 @@ step_kernel(StepArgs<T> a, int64_t n, const T* __restrict__ src, T* __restrict__
   __shared__ T s_bfp[RB][9][LR];
 
   // XCD-aware order: consecutive blocks go round-robin to the 8 XCDs, so give
-  // each XCD a contiguous band of tiles (shared halos stay in one L2)
-  const int per = (a.nlogical + 7) >> 3;
-  const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (logical >= a.nlogical) return;
-  const int strip = logical % a.nstrips;
-  const int seg = logical / a.nstrips;
+  // each XCD a contiguous band of tiles (shared halos stay in one L2).  With
+  // ileave = C > 1 the band is whole segments, cut into C chunks of clen
+  // segments whose tiles are taken in turn (segment i of every chunk, then
+  // i + 1, ...): a tile then starts about when the one below it in its strip
+  // ends, while the rows they share are still cached.  Blocks beyond the
+  // band's segments exit at once.
+  int strip, seg;
+  if (a.ileave <= 1) {
+    const int per = (a.nlogical + 7) >> 3;
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (logical >= a.nlogical) return;
+    strip = logical % a.nstrips;
+    seg = logical / a.nstrips;
+  } else {
+    const int x = blockIdx.x & 7;
+    const int v = blockIdx.x >> 3;
+    const int row = v / a.nstrips;
+    strip = v - row * a.nstrips;
+    const int i = row / a.ileave, c = row - i * a.ileave;
+    const int s0 = x * a.nsegs / 8, s1 = (x + 1) * a.nsegs / 8;
+    const int rel = c * a.clen + i;
+    if (rel >= s1 - s0) return;
+    seg = s0 + rel;
+  }
 
   // the LDS pads are never read into owned results; keep them finite
   for (int j = threadIdx.x; j < RB * 9 * LR; j += LANES) (&s_bfp[0][0][0])[j] = T(0);

@@ -77,6 +77,10 @@ inline StepArgs<T> step_args(const dugks_plan* P, int stage = STAGE_T2) {
   a.nstrips = P->nstrips;
   a.nsegs = P->nsegs;
   a.nlogical = P->nstrips * P->nsegs;
+  // interleave two chunks of each XCD's band once it holds 4 segments or more
+  // (not for the wide patch: one wavefront per SIMD, and it measured slower)
+  a.ileave = P->nsegs >= 32 && !wide(P->p.recon) ? 2 : 1;
+  a.clen = ((P->nsegs + 7) / 8 + a.ileave - 1) / a.ileave;
   a.ngroups = L.ngroups;
   const dugks_plan::StageCoef& c = P->st[stage];
   a.cB2 = T(c.cbar);
