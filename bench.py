@@ -452,11 +452,18 @@ def cpu_baseline(w):
         others[f"{name} {wl['nx']}x{wl['ny']}, {steps} steps"] = {
             "mlups": round(v, 2), "seconds": round(dt, 2)}
     v, dt = sample(w, CPU_STEPS)
+    cores = oracle.threads()
+    # one core: the 256^2 case again
+    oracle.set_threads(1)
+    v1, dt1 = sample(I.workload("c2"), 40)
+    oracle.set_threads(cores)
     return {"value": round(v, 2), "unit": "MLUPS",
-            "cores": oracle.threads(), "cpu": _cpu_model(), "kind": "oracle",
+            "cores": cores, "cpu": _cpu_model(), "kind": "oracle",
             "sample": f"{CPU_STEPS} steps (n=0..{CPU_STEPS - 1}) of the {w['nx']}x{w['ny']} "
                       f"workload, FP64, {dt:.1f} s",
-            "other_samples": others}
+            "other_samples": others,
+            "single_thread": {"c2 256x256, 40 steps": {"mlups": round(v1, 2),
+                                                       "seconds": round(dt1, 2)}}}
 
 
 def main():

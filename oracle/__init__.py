@@ -100,6 +100,8 @@ def lib(variant: str = "plain"):
         L.oracle_aux_shift.argtypes = [ctypes.c_double] * 6
         L.oracle_aux_shift.restype = ctypes.c_double
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         _libs[variant] = L
     return _libs[variant]
 
@@ -238,6 +240,11 @@ def velocity(params: Params, x: float, y: float, t: float):
 
 def threads() -> int:
     return lib().oracle_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's loops from now on (e.g. 1 to time one core)."""
+    lib().oracle_set_threads(int(n))
 
 
 def e_phi(phi_t: np.ndarray, phi_0: np.ndarray) -> float:

@@ -91,6 +91,15 @@ int oracle_threads(void) {
 #endif
 }
 
+/* threads of the loops from now on (timing the oracle on one core) */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- velocity */
 /* Analytic prescribed fields (Sec. III; Eq. 43 rotation, Eq. 45 deformation):
  *  UNIFORM       u = p0, v = p1

@@ -87,6 +87,7 @@ double oracle_mass(int nx, int ny, const double *tf);
 
 /* Number of OpenMP threads the oracle runs on (1 without OpenMP). */
 int oracle_threads(void);
+void oracle_set_threads(int n);
 
 #ifdef __cplusplus
 }
