@@ -89,11 +89,13 @@ def _e_final(c: dict, phi: np.ndarray, phi0: np.ndarray) -> float:
     return e_phi(phi, phi0)
 
 
-def run_alone(cases: list[dict], flags: int = 0) -> list[float | None]:
+def run_alone(cases: list[dict], flags: int = 0, progress=None) -> list[float | None]:
     """Each configuration on its own (per-step launches); None where the
-    scheme does not allow it."""
+    scheme does not allow it.  `progress(done, total)` is called after each."""
     out = []
-    for c in cases:
+    for k, c in enumerate(cases):
+        if progress and k:
+            progress(k, len(cases))
         if not allowed(c):
             out.append(None)
             continue
@@ -187,10 +189,11 @@ def _table(table, r, translation, zalesak, deformation):
     raise KeyError(table)
 
 
-def run_table(table: str, scheme: str, flags: int = 0) -> dict:
+def run_table(table: str, scheme: str, flags: int = 0, progress=None) -> dict:
     cols, cfgs = table_configs(table, scheme)
     # the fifth-order reconstruction runs on single grids (no batch form)
-    e = run_alone(cfgs, flags) if SCHEMES[scheme][0] == C.UPWIND5 else run(cfgs, flags=flags)
+    e = (run_alone(cfgs, flags, progress) if SCHEMES[scheme][0] == C.UPWIND5
+         else run(cfgs, flags=flags))
     return {f"CFL{c}": dict(zip([str(x) for x in cols], e[k * len(cols):(k + 1) * len(cols)]))
             for k, c in enumerate(CFLS)}
 
@@ -198,7 +201,9 @@ def run_table(table: str, scheme: str, flags: int = 0) -> dict:
 # Printed values read as misprints (see the notes in tests/golden/paper_tables.json):
 # (table, scheme, CFL key, column) -> the corrected reading
 MISPRINTS = {("IX", "T2S3", "CFL0.5", 0.1): 9.55e-3,
-             ("III", "T3S3", "CFL0.25", 0.05): 1.09e-2}
+             ("III", "T3S3", "CFL0.25", 0.05): 1.09e-2,
+             ("VIII", "T2S5", "CFL0.25", 1280): 6.99e-3,
+             ("VIII", "T2S5", "CFL0.25", 1638.4): 8.49e-3}
 
 
 def compare(out: dict, golden: dict) -> dict:
@@ -227,7 +232,8 @@ def main(argv=None) -> int:
     import json
     import sys
     ap = argparse.ArgumentParser(description="Run the paper's DUGKS tables (T2S2CD, T2S3, "
-                                 "T3S3) on the GPU and print E_phi of every entry as JSON.")
+                                 "T3S3, T2S5) on the GPU and print E_phi of every entry as "
+                                 "JSON.")
     ap.add_argument("tables", nargs="*", default=["I", "II", "III", "IV", "V", "VIII", "IX"])
     ap.add_argument("--schemes", nargs="*", default=list(SCHEMES))
     ap.add_argument("--compare", metavar="GOLDEN_JSON", default=None,
@@ -239,7 +245,9 @@ def main(argv=None) -> int:
     out = {}
     for t in args.tables:
         for s in args.schemes:
-            out[f"{t}/{s}"] = run_table(t, s)
+            def note(done, total, t=t, s=s):
+                print(f"table {t} {s}: {done}/{total}", file=sys.stderr, flush=True)
+            out[f"{t}/{s}"] = run_table(t, s, progress=note)
             print(f"table {t} {s} done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     if args.compare:

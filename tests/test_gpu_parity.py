@@ -260,14 +260,17 @@ def test_cfl_one_and_theta_off(gpu, orc):
     _check(g, o, "no d(phi u)/dt", orc)
 
 
-def test_tile_shape_invariance_bitwise(gpu):
+@pytest.mark.parametrize("nx,ny,tiles", [(150, 97, (0, 1, 5, 16, 33, 97)),
+                                         (150, 400, (0, 8, 16, 56, 400))])
+def test_tile_shape_invariance_bitwise(gpu, nx, ny, tiles):
     """Every tile height gives the same bits: each cell's arithmetic does not
-    depend on which wavefront computes it."""
-    nx, ny = 150, 97
+    depend on which wavefront computes it.  The 400-row grid in 8-row tiles
+    (50 segments) takes the interleaved tile order, with bands of 6 and 7
+    segments; its other heights the plain one."""
     phi0 = I.random_circles(nx, ny, 6, 6.0, 20.0, 4.0, seed=3)
     for precision in (0, 1):
         ref = None
-        for tile in (0, 1, 5, 16, 33, 97):
+        for tile in tiles:
             g = gpu(nx, ny, 0.01, 4.0, 0.5, recon=1, precision=precision,
                     vel_kind=2, vel_param=(0.05, 400.0), tile_rows=tile).init(phi0)
             g.step(25)
