@@ -249,7 +249,6 @@ struct Marcher {
   double macc, mcnt;
   double* part_row;
 
-  __device__ __forceinline__ T cw(int i) const { return i == 0 ? cw0 : ((i & 1) ? cw1 : cw2); }
 
   // VARR: component c (0: u, 1: v) at the lane's cell of (wrapped) row rr;
   // rows are read again at the faces two rows later, from the caches
@@ -271,9 +270,12 @@ struct Marcher {
 #pragma unroll
     for (int i = 0; i < 9; i++) d.f[i] = p[i * OWN];
     if (FIX_LOAD) {
+      // the pending w_i delta of the cell's weight class, or 0 (one select
+      // per class instead of one per plane)
       const bool fit = d.f[0] < fitmax;
+      const T c0 = fit ? cw0 : T(0), c1 = fit ? cw1 : T(0), c2 = fit ? cw2 : T(0);
 #pragma unroll
-      for (int i = 0; i < 9; i++) d.f[i] = fit ? d.f[i] + cw(i) : d.f[i];
+      for (int i = 0; i < 9; i++) d.f[i] += i == 0 ? c0 : ((i & 1) ? c1 : c2);
     }
     d.hp = p[9 * OWN];
     if (WIDE && (lane == 0 || lane == LANES - 1)) {
@@ -282,8 +284,9 @@ struct Marcher {
       for (int i = 0; i < 9; i++) d.g[i] = q[i * OWN];
       if (FIX_LOAD) {
         const bool fit = d.g[0] < fitmax;
+        const T c0 = fit ? cw0 : T(0), c1 = fit ? cw1 : T(0), c2 = fit ? cw2 : T(0);
 #pragma unroll
-        for (int i = 0; i < 9; i++) d.g[i] = fit ? d.g[i] + cw(i) : d.g[i];
+        for (int i = 0; i < 9; i++) d.g[i] += i == 0 ? c0 : ((i & 1) ? c1 : c2);
       }
     }
   }
@@ -500,7 +503,7 @@ struct Marcher {
           const T v = tfp + out[i];
           bstore(v, rdst, ob + i * PL);
           if (FIX_SUM) {
-            cs += owned ? (double)v : 0.0;
+            cs += (double)v;
             if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
           }
         }
@@ -534,7 +537,7 @@ struct Marcher {
           const T v = fma(a.wo1, out[i], fma(a.kap, dx, qv[i]));
           bstore(v, rdst, ob + i * PL);
           if (FIX_SUM) {
-            cs += owned ? (double)v : 0.0;
+            cs += (double)v;
             if (i == 0 && owned && v < T(MASS_FIT_MAX)) cf0 = 1.0;
           }
         }
@@ -542,10 +545,11 @@ struct Marcher {
       }
     }
     if (FIX_SUM) {
-      // phi^{n+1} of the row into the group total; a group never straddles
-      // two segments (segments are whole groups), so its sum -- lanes in a
-      // fixed butterfly after rows in order -- does not depend on the tiling
-      macc += cs;
+      // phi^{n+1} of the row (owned lanes) into the group total; a group
+      // never straddles two segments (segments are whole groups), so its sum
+      // -- lanes in a fixed butterfly after rows in order -- does not depend
+      // on the tiling
+      macc += owned ? cs : 0.0;
       mcnt += cf0;
       const bool gend = (k & (MASS_GROUP - 1)) == MASS_GROUP - 1 || k == a.ny - 1;
       double v = 0.0, w = 0.0;
