@@ -12,15 +12,21 @@ __all__ = ["_lib", "build", "inputs", "solver"]
 def kernel_fingerprint() -> str:
     """Hash of what defines the step kernels -- their device sources, the
     host code that sets their arguments and tile order (dugks_plan.h), and
-    the compiler flags; profile summaries record it so a counter measurement
-    is only reused for the kernel it was taken on."""
+    the compiler flags, with comments and layout left out; profile summaries
+    record it so a counter measurement is only reused for the kernel it was
+    taken on."""
     import hashlib
     import os
+    import re
     from . import build
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
     for name in ("dugks_common.h", "dugks_kernels.h", "dugks_plan.h"):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(d, name), encoding="utf-8") as f:
+            code = f.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        code = " ".join(code.split())
+        h.update(name.encode() + b"\0" + code.encode())
     h.update(" ".join(build.FLAGS).encode())
     return h.hexdigest()[:16]

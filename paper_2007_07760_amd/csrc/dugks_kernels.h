@@ -878,8 +878,8 @@ __device__ __forceinline__ void mass_fix_block(const double* __restrict__ part,
 // the slot is attached) and a step counter pair (n, target) that the finish
 // kernel advances; a grid with n >= target is idle.  The work list holds one
 // item per (slot, tile) -- tile = seg * nstrips + strip, with the slot's own
-// segment height -- and wavefronts take items from a queue head in device
-// memory until the list is exhausted.
+// segment height -- and wavefronts take items from queue heads in device
+// memory (one queue per XCD, see NQUEUE) until the list is exhausted.
 template <typename T>
 struct GridDesc {
   StepArgs<T> a;      // T2, or T3S3 stage A
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(LANES, step_waves(sizeof(T), R, MFIX)) void batch_s
 }
 
 // After each batch step: per active slot, the fused mass correction (MFIX)
-// and n += 1; block 0 rewinds the work queue for the next step.
+// and n += 1; block 0 rewinds the work queues for the next step.
 // A slot whose state reports a non-finite total (status ENUMERIC: from its
 // first state, or from this step's fused correction) stops here: its target
 // becomes the step it has reached, and the status is kept for the caller.
