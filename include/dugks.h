@@ -344,7 +344,8 @@ int dugks_batch_tune(dugks_batch *batch, int32_t reps, int32_t *rows_out,
  * independent grids without a batch: grid j (plans[j], states[j], initialised
  * by dugks_init, currently at step steps[j]) advances by nsteps steps, each
  * step one persistent launch of the batch step kernel over every grid's tiles
- * (two for T3S3) and the finish kernel; results are bitwise those of
+ * (two for T3S3; each grid whole in one of the per-XCD work queues) and the
+ * finish kernel; results are bitwise those of
  * dugks_step and of a batch.  Nothing is allocated: descriptors, step
  * counters, slot status and the work list live in one fixed 1 MiB device
  * array of the library per GPU, filled by small set-up kernels whose inputs

@@ -56,12 +56,14 @@ __global__ __launch_bounds__(64) void noalloc_desc_kernel(DescChunk<T> c, unsign
 }
 
 // the work list: item i belongs to the grid j with start[j] <= i < start[j+1]
-// (grids in decreasing order of tile height), tile i - start[j]; one thread
+// (grids by queue, then in decreasing order of tile height), tile
+// i - start[j]; queue q holds items [qstart[q], qstart[q+1]).  One thread
 // also writes the control block and rewinds the queue heads
 struct ItemStarts {
   int32_t start[NOALLOC_GRIDS + 1];
   int32_t grid[NOALLOC_GRIDS];
-  int n;
+  int32_t qstart[NQUEUE + 1];
+  int n, nq;
 };
 static_assert(sizeof(ItemStarts) <= 4096, "kernel argument size");
 
@@ -74,8 +76,8 @@ static __global__ __launch_bounds__(256) void noalloc_items_kernel(ItemStarts a,
     BatchCtl* ctl = reinterpret_cast<BatchCtl*>(base + NA_CTL);
     ctl->items = items;
     ctl->nitems = nitems;
-    ctl->nq = 1;   // one queue: the list is in order of tile height only
-    for (int q = 0; q <= NQUEUE; q++) ctl->qstart[q] = q == 0 ? 0 : nitems;
+    ctl->nq = a.nq;
+    for (int q = 0; q <= NQUEUE; q++) ctl->qstart[q] = a.qstart[q];
     unsigned* head = reinterpret_cast<unsigned*>(base + NA_HEAD);
     for (int q = 0; q < NQUEUE; q++) head[q * HEAD_STRIDE] = head[q * HEAD_STRIDE + 1] = 0u;
   }
@@ -154,8 +156,10 @@ int dugks_step_many_noalloc(const dugks_plan* const* plans, void* const* states,
   if (!p0) return DUGKS_EINVAL;
   const int precision = p0->p.precision, recon = p0->p.recon, scheme = p0->p.scheme;
   const bool mfix = (p0->p.flags & DUGKS_FLAG_MASS_FIX) != 0;
-  // tiles per grid (each grid at its plan's own segment height), grids in
-  // decreasing order of that height so that the short tiles fill the tail
+  // tiles per grid (each grid at its plan's own segment height); each grid
+  // whole to one of the NQUEUE queues (one per XCD), the largest first to
+  // the least loaded; within a queue the grids in decreasing order of tile
+  // height, so that the short tiles fill the tail
   ItemStarts starts;
   memset(&starts, 0, sizeof(starts));
   starts.n = n;
@@ -170,17 +174,37 @@ int dugks_step_many_noalloc(const dugks_plan* const* plans, void* const* states,
       return DUGKS_EUNSUPPORTED;
     order[j] = j;
   }
-  std::stable_sort(order, order + n, [plans](int a, int b) {
+  // rows a grid's tiles march in all
+  auto work = [plans](int j) {
+    const dugks_plan* P = plans[j];
+    return (int64_t)P->nstrips * ((int64_t)P->p.ny + 5 * (int64_t)P->nsegs);
+  };
+  std::stable_sort(order, order + n, [&](int a, int b) { return work(a) > work(b); });
+  int queue_of[NOALLOC_GRIDS];
+  int64_t load[NQUEUE] = {};
+  for (int k = 0; k < n; k++) {
+    int q = 0;
+    for (int r = 1; r < NQUEUE; r++)
+      if (load[r] < load[q]) q = r;
+    queue_of[order[k]] = q;
+    load[q] += work(order[k]);
+  }
+  std::stable_sort(order, order + n, [&](int a, int b) {
+    if (queue_of[a] != queue_of[b]) return queue_of[a] < queue_of[b];
     return plans[a]->seg_rows > plans[b]->seg_rows;
   });
+  starts.nq = NQUEUE;
   int64_t total = 0;
+  int q = 0;
   for (int k = 0; k < n; k++) {
     const dugks_plan* P = plans[order[k]];
+    while (q <= queue_of[order[k]]) starts.qstart[q++] = (int32_t)total;
     starts.start[k] = (int32_t)total;
     starts.grid[k] = order[k];
     total += (int64_t)P->nstrips * P->nsegs;
     if (total > NOALLOC_ITEMS) return DUGKS_EINVAL;   // beyond the array's work list
   }
+  while (q <= NQUEUE) starts.qstart[q++] = (int32_t)total;
   starts.start[n] = (int32_t)total;
   if (nsteps == 0) return DUGKS_OK;
   unsigned char* base = nullptr;
