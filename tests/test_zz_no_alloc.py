@@ -24,14 +24,17 @@ def lib():
     return _lib
 
 
-def _grids(lib, specs, precision, flags):
+def _grids(lib, specs, precision, flags, scheme=0):
     from paper_2007_07760_amd.solver import Solver
     out = []
+    # T3S3 needs dt < 12 tau = 36 M
+    mobility = 0.02 if scheme else 0.01
     for k, (nx, ny, kind, prm) in enumerate(specs):
         r = min(nx, ny)
         phi0 = I.random_circles(nx, ny, 1 + k % 3, 0.1 * r, 0.3 * r, 4.0, seed=50 + k)
-        out.append(Solver(nx, ny, 0.01, 4.0, 0.5, recon=lib.UPWIND3, precision=precision,
-                          vel_kind=kind, vel_param=prm, flags=flags).init(phi0))
+        out.append(Solver(nx, ny, mobility, 4.0, 0.5, recon=lib.UPWIND3, precision=precision,
+                          vel_kind=kind, vel_param=prm, flags=flags,
+                          scheme=scheme).init(phi0))
     return out
 
 
@@ -45,9 +48,9 @@ def _noalloc(lib, solvers, nsteps):
         s.step_index += nsteps
 
 
-def _batched(lib, solvers, nsteps, precision, flags):
+def _batched(lib, solvers, nsteps, precision, flags, scheme=0):
     from paper_2007_07760_amd.batch import Batch
-    b = Batch(len(solvers), precision, lib.UPWIND3, flags)
+    b = Batch(len(solvers), precision, lib.UPWIND3, flags | (lib.BATCH_T3S3 if scheme else 0))
     for k, s in enumerate(solvers):
         b.set(k, s, s.step_index + nsteps)
     b.commit()
@@ -60,15 +63,15 @@ FIRST = [(130, 96, 1, (0.0008, 65.0, 48.0)), (64, 200, 2, (0.05, 900.0)),
 SECOND = [(40, 24, 0, (0.03, -0.02)), (20, 33, 1, (0.001, 10.0, 16.0))]
 
 
-@pytest.mark.parametrize("precision,flags", [(1, 2), (0, 0)])
-def test_noalloc_equals_batch_two_calls(lib, precision, flags):
+@pytest.mark.parametrize("precision,flags,scheme", [(1, 2, 0), (0, 0, 0), (0, 0, 1), (1, 2, 1)])
+def test_noalloc_equals_batch_two_calls(lib, precision, flags, scheme):
     import torch
-    print(f"case noalloc prec={precision} flags={flags}", flush=True)
+    print(f"case noalloc prec={precision} flags={flags} scheme={scheme}", flush=True)
     for specs, nsteps in ((FIRST, 17), (SECOND, 6)):
-        a = _grids(lib, specs, precision, flags)
-        b = _grids(lib, specs, precision, flags)
+        a = _grids(lib, specs, precision, flags, scheme)
+        b = _grids(lib, specs, precision, flags, scheme)
         _noalloc(lib, a, nsteps)
-        _batched(lib, b, nsteps, precision, flags)
+        _batched(lib, b, nsteps, precision, flags, scheme)
         for k in range(len(specs)):
             assert a[k].step_index == b[k].step_index == nsteps
             assert torch.equal(a[k].distributions(), b[k].distributions()), (specs[k], k)
